@@ -1,0 +1,231 @@
+"""Benchmark of the MG-preconditioned XDG solve on one MI355X.
+
+Workload: 3D SIP Poisson, p = 3 (20 modes/species/cell), 32^3 cut grid on
+[-1,1]^3, sphere r = 0.6 with seeded centre jitter, diffusivity 1 | 1000,
+alpha = 0.1, RHS ~ U[-1,1] per coefficient, 4-level aggregation + p multigrid
+V-cycle with damped block Jacobi (2 pre / 2 post, omega 0.7), FP64 CG.
+
+One step = the whole hot path on device-resident input: numeric hierarchy
+set-up from the level-0 values (Galerkin products, cell-block and coarsest
+inversions; xdg_update_matrix) followed by the PCG solve to rel.res 1e-8
+(xdg_solve).  `value` is the time of one step in seconds (lower is better).
+The JSON line also carries the level-0 block-SpMV roofline (HIP events around
+back-to-back launches on the solver's stream), the time to 1e-10, the
+mixed-precision FGMRES form and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(pr, word=8):
+    nnzb, npm, rows = pr.col_idx.size, pr.np, pr.n_rows
+    return nnzb * npm * npm * word + 4 * nnzb + 4 * (rows + 1) + 2 * rows * npm * word
+
+
+def time_spmv(torch, B, S, level, reps=50):
+    n = S.level_len(level)
+    xs = [S.vec(level, np.random.default_rng(k).uniform(-1, 1, n)) for k in range(2)]
+    y = S.vec(level)
+    for k in range(3):
+        B.xdg_spmv(S.h, level, xs[k % 2], y)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for k in range(reps):
+        B.xdg_spmv(S.h, level, xs[k % 2], y)
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3   # seconds per launch
+
+
+def cpu_baseline(pr, gpu_iters, budget_iters=8):
+    """The oracle as it stands on the host: hierarchy set-up plus a few PCG
+    iterations, scaled to the GPU's iteration count."""
+    from threadpoolctl import threadpool_limits
+    from oracle import mg
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        H = mg.hierarchy_of(pr)
+        t1 = time.perf_counter()
+        mg.pcg(H.A[0], pr.b, H.vcycle, rtol=0.0, maxit=budget_iters)
+        t2 = time.perf_counter()
+    per_it = (t2 - t1) / budget_iters
+    est = (t1 - t0) + per_it * gpu_iters
+    return dict(value=round(est, 3), unit="s", cores=1, kind="oracle",
+                sample=f"oracle Galerkin hierarchy set-up ({t1 - t0:.1f} s) + {budget_iters} "
+                       f"PCG iterations ({per_it:.2f} s each) on the same 32^3 p=3 problem, "
+                       f"scaled to the GPU's {gpu_iters} iterations to rel.res 1e-8")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--profile-spmv", action="store_true",
+                    help="only launch the level-0 SpMV 20 times and a plain copy (counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2003_02431_amd import binding as B
+    from xdg_inputs import problems
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"[bench] generating c2 workload n={args.n} seed={args.seed}")
+    t0 = time.time()
+    pr = problems.c2(seed=args.seed, n=args.n)
+    log(f"[bench] generated rows={pr.n_rows} nnzb={pr.col_idx.size} in {time.time() - t0:.1f}s")
+
+    opt8 = B.options(krylov=B.XDG_CG, rtol=1e-8, maxit=1000)
+    S = B.Solver(pr, opt8)
+    log(f"[bench] handle created, set-up {B.xdg_setup_time(S.h):.1f} ms")
+    if args.profile_spmv:
+        n = S.level_len(0)
+        x = S.vec(0, np.random.default_rng(0).uniform(-1, 1, n))
+        y = S.vec(0)
+        for _ in range(20):
+            B.xdg_spmv(S.h, 0, x, y)
+        big = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        out = torch.empty_like(big)
+        out.copy_(big)
+        torch.cuda.synchronize()
+        log(f"[bench] profile-spmv: 20 launches, bytes/launch {spmv_bytes(pr)}; copy 1 GiB")
+        return
+
+    val_dev = torch.as_tensor(np.ascontiguousarray(pr.val)).cuda()
+    b_dev = S.vec(0, pr.b)
+    x_dev = S.vec(0)
+
+    def step():
+        B.xdg_update_matrix(S.h, val_dev)
+        x_dev.zero_()
+        return B.xdg_solve(S.h, b_dev, x_dev, hist_cap=2000)
+
+    for w in range(args.warmup):
+        rc, it, fr, _ = step()
+        log(f"[bench] warmup {w}: status {rc} iters {it} relres {fr:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for k in range(args.steps):
+        rc, it, fr, hist = step()
+        its.append(it)
+        assert rc == 0, f"solve failed with status {rc}"
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    log(f"[bench] {args.steps} steps: {dt * 1e3:.2f} ms/step, iters {its}, relres {fr:.2e}")
+    setup_ms = B.xdg_setup_time(S.h)
+
+    # time to 1e-10 (config's own tolerance) and the iterate error of the 1e-8 stop
+    S10 = B.Solver(pr, B.options(krylov=B.XDG_CG, rtol=1e-10, maxit=1000))
+    x10 = S10.vec(0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.xdg_update_matrix(S10.h, val_dev)
+    rc10, it10, fr10, _ = B.xdg_solve(S10.h, b_dev, x10, hist_cap=2000)
+    torch.cuda.synchronize()
+    dt10 = time.perf_counter() - t1
+    log(f"[bench] to 1e-10: {dt10 * 1e3:.2f} ms, iters {it10}")
+    Stight = B.Solver(pr, B.options(krylov=B.XDG_CG, rtol=1e-13, maxit=2000))
+    xt = Stight.vec(0)
+    B.xdg_solve(Stight.h, b_dev, xt, hist_cap=3000)
+    Stight.close()
+    err8 = float(torch.linalg.norm(x_dev - xt) / torch.linalg.norm(xt))
+    S10.close()
+
+    mixed = None
+    if not args.no_mixed:
+        Sm = B.Solver(pr, B.options(krylov=B.XDG_FGMRES, restart=30, precision=B.XDG_MIXED,
+                                    rtol=1e-8, maxit=1000))
+        xm = Sm.vec(0)
+        B.xdg_update_matrix(Sm.h, val_dev)
+        B.xdg_solve(Sm.h, b_dev, xm, hist_cap=2000)     # warm-up
+        tm = []
+        for _ in range(3):
+            xm.zero_()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            B.xdg_update_matrix(Sm.h, val_dev)
+            rcm, itm, frm, _ = B.xdg_solve(Sm.h, b_dev, xm, hist_cap=2000)
+            torch.cuda.synchronize()
+            tm.append(time.perf_counter() - t2)
+        errm = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
+        mixed = dict(time_s=round(float(np.median(tm)), 5), iters=itm, relres=frm,
+                     err_vs_fp64=errm, krylov="FGMRES(30)",
+                     note="FP32 V-cycle (A, D^-1, R in FP32), FP64 Arnoldi, SpMV in "
+                          "Arnoldi, residuals and coarsest inverse")
+        log(f"[bench] mixed: {tm} iters {itm} relres {frm:.2e} err {errm:.2e}")
+        Sm.close()
+
+    # roofline of the level-0 block SpMV
+    t_spmv = time_spmv(torch, B, S, 0)
+    nbytes = spmv_bytes(pr)
+    achieved = nbytes / t_spmv / 1e9
+    log(f"[bench] spmv: {t_spmv * 1e6:.1f} us/launch, {achieved:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) on a bounded sample")
+        cpu = cpu_baseline(pr, int(np.median(its)))
+        log(f"[bench] cpu baseline {cpu}")
+
+    out = {
+        "metric": "MG-solve time to rel.res 1e-8 (s) & block-SpMV HBM GB/s, 3D p=3 cut grid",
+        "value": round(dt, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"xdg_sip_poisson_3d_p3_{args.n}^3_sphere_r0.6_mu1:1000",
+                   "block_rows": int(pr.n_rows), "np": int(pr.np),
+                   "nnzb": int(pr.col_idx.size), "dofs": int(pr.n_rows * pr.np),
+                   "levels": len(pr.transfers) + 1, "krylov": "CG", "smoother":
+                   "block-Jacobi 2+2 omega=0.7", "seed": args.seed},
+        "iters_to_1e-8": int(np.median(its)),
+        "setup_ms": round(setup_ms, 3),
+        "time_to_1e-10_s": round(dt10, 6),
+        "iters_to_1e-10": it10,
+        "err_at_1e-8_vs_tight_fp64": err8,
+        "mixed_precision": mixed,
+        "spmv_gbs": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_bsr_spmv<double,20> level 0",
+                     "bytes_per_launch": int(nbytes), "us_per_launch": round(t_spmv * 1e6, 2)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    S.close()
+
+
+if __name__ == "__main__":
+    main()

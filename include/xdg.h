@@ -1,0 +1,162 @@
+/*
+ * libxdg -- multigrid-preconditioned solve of the agglomerated cut-cell SIP
+ * system of the extended discontinuous Galerkin (XDG) method on one MI355X.
+ *
+ * The linear system is the matrix form of the discretisation on the
+ * agglomerated XDG space (paper Section 3.2, Eq. GenericMatrixSystem):
+ *     M U = b,  M[m(j,s,n), m(l,r,k)] = a(Phi_{l,r,k}, Phi_{j,s,n}),
+ * one block row per (aggregate cell, species), Np = dim P_k modes per block.
+ * Coarse levels come from transfer matrices R^{X,lambda} (Eq.
+ * XDGrestrictionMatrix) through the Galerkin product
+ * M^{lambda+1} = R^T M^lambda R (Eq. XDGsysRestriction).
+ *
+ * Conventions for every call:
+ *   - return value: 0 = XDG_OK, > 0 warning, < 0 error; no call aborts or
+ *     throws across this interface; xdg_last_error() describes the last
+ *     failure of the calling thread.
+ *   - host arrays passed to xdg_create are owned by the caller and may be
+ *     freed when it returns (everything is copied to the device).
+ *   - *_dev pointers are caller-owned device buffers on the handle's device;
+ *     outputs must not alias inputs.
+ *   - every call is enqueued on the handle's HIP stream; only xdg_create,
+ *     xdg_solve and the xdg_get_* copies synchronise it.
+ *   - vectors are FP64, laid out [block row][mode] (row-major), length
+ *     n_rows * np of the level they live on.
+ */
+#ifndef XDG_H
+#define XDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    XDG_OK = 0,
+    XDG_ENOCONV = 1,      /* iteration limit reached; x and history are valid  */
+    XDG_EINVAL = -1,      /* bad sizes/indices, unsorted rows, NaN/Inf input   */
+    XDG_ENOMEM = -2,      /* device allocation failed                          */
+    XDG_EHIP = -3,        /* HIP runtime error                                 */
+    XDG_ENOTSPD = -4,     /* non-positive pivot in a cell block or the coarse  */
+                          /* matrix                                            */
+    XDG_EBREAKDOWN = -5   /* Krylov breakdown (p^T A p <= 0 or zero Arnoldi)   */
+};
+
+enum { XDG_T_PTRUNC = 0, XDG_T_DENSE = 1 };
+enum { XDG_CG = 0, XDG_FGMRES = 1 };
+enum { XDG_FP64 = 0, XDG_MIXED = 1 };
+enum { XDG_JACOBI = 0, XDG_LEARNED = 1 };
+
+typedef struct xdg_handle xdg_handle;
+
+/* Level-0 system matrix (host memory, caller-owned).
+ * Block rows are (aggregate, species) pairs (Section 3.2, index convention);
+ * block b of row i holds M[m(i, r), m(col_idx[b], c)] = val[b*np*np + r*np + c].
+ * col_idx must be sorted within each row and contain the diagonal.
+ * Smoother cell blocks: cell c owns the consecutive block rows
+ * [cell_ptr[c], cell_ptr[c+1]) (all species of one representative cell, the
+ * blocks m(j,-,-,.) of Section 3.3). */
+typedef struct {
+    int32_t n_rows, np, nnzb;
+    const int32_t *row_ptr;   /* [n_rows + 1], row_ptr[0] = 0, row_ptr[n_rows] = nnzb */
+    const int32_t *col_idx;   /* [nnzb] */
+    const double  *val;       /* [nnzb * np * np] */
+    int32_t n_cells;
+    const int32_t *cell_ptr;  /* [n_cells + 1] */
+} xdg_matrix;
+
+/* Transfer from level lambda (fine, n_rows_f x np_f) to lambda+1 (Section 3.2).
+ * kind XDG_T_PTRUNC: same block rows, the coarse space keeps the leading np_c
+ *   modes of every block (graded orthonormal bases: R_i = [I; 0]); parent and
+ *   R are ignored (may be NULL).
+ * kind XDG_T_DENSE: fine row i lies in coarse row parent[i]; its projection
+ *   block R_i (np_f x np_c, row-major) is R[i*np_f*np_c + a*np_c + m] =
+ *   int_{P_i} phi_{i,a} phi_{parent(i),m}. */
+typedef struct {
+    int32_t kind, n_rows_c, np_c;
+    const int32_t *parent;    /* [n_rows_f] */
+    const double  *R;         /* [n_rows_f * np_f * np_c] */
+    int32_t n_cells_c;
+    const int32_t *cell_ptr_c;/* [n_cells_c + 1] coarse smoother blocks */
+} xdg_transfer;
+
+typedef struct {
+    int32_t krylov;           /* XDG_CG (needs precision XDG_FP64) | XDG_FGMRES */
+    int32_t restart;          /* FGMRES restart length (<= 64)                  */
+    int32_t maxit;            /* Krylov iteration limit                         */
+    int32_t nu_pre, nu_post;  /* block-Jacobi sweeps per level                  */
+    int32_t precision;        /* XDG_FP64 | XDG_MIXED (FP32 V-cycle)            */
+    int32_t smoother;         /* XDG_JACOBI                                     */
+    int32_t nrhs;             /* 1                                              */
+    double  rtol;             /* stop at ||b - M x||_2 / ||b||_2 <= rtol        */
+    double  omega;            /* Jacobi damping                                 */
+} xdg_options;
+
+/* Copies the level-0 system and transfers to the device, forms every coarse
+ * level by the Galerkin product, inverts every smoother cell block (FP64
+ * Gauss-Jordan) and the coarsest matrix, and (XDG_MIXED) makes FP32 copies.
+ * hip_stream: a hipStream_t (NULL = default stream).  On error *out is NULL. */
+int xdg_create(const xdg_matrix *A0, int32_t n_levels, const xdg_transfer *T,
+               const xdg_options *opt, void *hip_stream, xdg_handle **out);
+
+/* y = M^lambda x on level `level` (Eq. GenericMatrixSystem). */
+int xdg_spmv(xdg_handle *h, int32_t level, const double *x_dev, double *y_dev);
+
+/* `sweeps` damped block-Jacobi sweeps x <- x + omega D^{-1} (b - M x) on
+ * `level`, D the cell-block diagonal; x is updated in place. */
+int xdg_smooth(xdg_handle *h, int32_t level, const double *b_dev, double *x_dev,
+               int32_t sweeps);
+
+/* rc = (R^{X,level})^T rf : fine level `level` -> level+1. */
+int xdg_restrict(xdg_handle *h, int32_t level, const double *rf_dev, double *rc_dev);
+
+/* xf += R^{X,level} xc : level+1 -> fine level `level`. */
+int xdg_prolong(xdg_handle *h, int32_t level, const double *xc_dev, double *xf_dev);
+
+/* z = B r, one symmetric V-cycle from level 0 (pre-smoothing from zero,
+ * coarse-grid correction, post-smoothing, exact coarsest solve). */
+int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
+
+/* Solves M^0 x = b.  x_dev holds the initial guess on entry and the solution
+ * on return.  hist_host[k] = ||r_k||_2/||b||_2, k = 0..*iters (at most
+ * hist_cap entries are written); *final_relres is the recomputed true FP64
+ * residual.  Returns XDG_ENOCONV (x valid) when maxit is reached. */
+int xdg_solve(xdg_handle *h, const double *b_dev, double *x_dev, double *hist_host,
+              int32_t hist_cap, int32_t *iters, double *final_relres);
+
+/* Level sizes (for callers allocating level vectors). */
+int xdg_level_info(xdg_handle *h, int32_t level, int32_t *n_rows, int32_t *np,
+                   int32_t *nnzb);
+
+/* Host copies of the device-built level matrix (row-major blocks) -- the
+ * Galerkin product for level > 0.  Arrays sized from xdg_level_info. */
+int xdg_get_level_matrix(xdg_handle *h, int32_t level, int32_t *row_ptr,
+                         int32_t *col_idx, double *val);
+
+/* Host copy of the inverse of smoother cell block `cell` on `level`
+ * (n x n row-major, n = rows_in_cell * np); *n receives its order.
+ * On the coarsest level, cell = 0 returns the inverse of the whole matrix. */
+int xdg_get_cell_inverse(xdg_handle *h, int32_t level, int32_t cell, double *out,
+                         int32_t cap, int32_t *n);
+
+/* New level-0 values with the sparsity pattern given at xdg_create: val_dev
+ * is a device buffer (caller-owned, nnzb*np*np FP64, row-major blocks as in
+ * xdg_matrix.val).  Recomputes every Galerkin level, every smoother inverse
+ * and the coarsest inverse on the device (the numeric part of xdg_create;
+ * the hierarchy set-up of the paper's phase (ii), Section 4).  Synchronises
+ * the stream; returns XDG_ENOTSPD on a non-positive pivot. */
+int xdg_update_matrix(xdg_handle *h, const double *val_dev);
+
+/* Milliseconds spent in xdg_create on the device (Galerkin products,
+ * inversions), measured with HIP events. */
+int xdg_setup_time(xdg_handle *h, double *ms);
+
+void xdg_destroy(xdg_handle *h);
+
+const char *xdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XDG_H */

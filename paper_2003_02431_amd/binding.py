@@ -1,0 +1,251 @@
+"""ctypes binding of libxdg (include/xdg.h): argument marshalling only.
+
+Device buffers are torch tensors (float64, on the handle's device); host
+arrays are numpy.  Every function raises XdgError on a negative status and
+returns a positive (warning) status unchanged.  The library must have been
+built (paper_2003_02431_amd/build.py); importing this module without it fails
+loudly -- there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxdg.so")
+
+XDG_OK, XDG_ENOCONV = 0, 1
+XDG_EINVAL, XDG_ENOMEM, XDG_EHIP, XDG_ENOTSPD, XDG_EBREAKDOWN = -1, -2, -3, -4, -5
+XDG_T_PTRUNC, XDG_T_DENSE = 0, 1
+XDG_CG, XDG_FGMRES = 0, 1
+XDG_FP64, XDG_MIXED = 0, 1
+XDG_JACOBI, XDG_LEARNED = 0, 1
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+
+
+class XdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libxdg error {code}: {msg}")
+        self.code = code
+
+
+class xdg_matrix(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("np", C.c_int32), ("nnzb", C.c_int32),
+                ("row_ptr", _i32p), ("col_idx", _i32p), ("val", _f64p),
+                ("n_cells", C.c_int32), ("cell_ptr", _i32p)]
+
+
+class xdg_transfer(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_rows_c", C.c_int32), ("np_c", C.c_int32),
+                ("parent", _i32p), ("R", _f64p), ("n_cells_c", C.c_int32),
+                ("cell_ptr_c", _i32p)]
+
+
+class xdg_options(C.Structure):
+    _fields_ = [("krylov", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
+                ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("precision", C.c_int32),
+                ("smoother", C.c_int32), ("nrhs", C.c_int32), ("rtol", C.c_double),
+                ("omega", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libxdg.so not built at {_LIB_PATH}; run paper_2003_02431_amd/build.py")
+    lib = C.CDLL(_LIB_PATH)
+    vp = C.c_void_p
+    sig = {
+        "xdg_create": ([C.POINTER(xdg_matrix), C.c_int32, C.POINTER(xdg_transfer),
+                        C.POINTER(xdg_options), vp, C.POINTER(vp)], C.c_int),
+        "xdg_spmv": ([vp, C.c_int32, vp, vp], C.c_int),
+        "xdg_smooth": ([vp, C.c_int32, vp, vp, C.c_int32], C.c_int),
+        "xdg_restrict": ([vp, C.c_int32, vp, vp], C.c_int),
+        "xdg_prolong": ([vp, C.c_int32, vp, vp], C.c_int),
+        "xdg_vcycle": ([vp, vp, vp], C.c_int),
+        "xdg_solve": ([vp, vp, vp, _f64p, C.c_int32, _i32p, _f64p], C.c_int),
+        "xdg_level_info": ([vp, C.c_int32, _i32p, _i32p, _i32p], C.c_int),
+        "xdg_get_level_matrix": ([vp, C.c_int32, _i32p, _i32p, _f64p], C.c_int),
+        "xdg_get_cell_inverse": ([vp, C.c_int32, C.c_int32, _f64p, C.c_int32, _i32p], C.c_int),
+        "xdg_update_matrix": ([vp, vp], C.c_int),
+        "xdg_setup_time": ([vp, _f64p], C.c_int),
+        "xdg_destroy": ([vp], None),
+        "xdg_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("xdg_create", "xdg_spmv", "xdg_smooth", "xdg_restrict", "xdg_prolong",
+            "xdg_vcycle", "xdg_solve", "xdg_level_info", "xdg_get_level_matrix",
+            "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_setup_time", "xdg_destroy",
+            "xdg_last_error")
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise XdgError(rc, _lib.xdg_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 torch tensor."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def options(krylov=XDG_CG, restart=30, maxit=500, nu_pre=2, nu_post=2, precision=XDG_FP64,
+            smoother=XDG_JACOBI, nrhs=1, rtol=1e-10, omega=0.7):
+    return xdg_options(krylov, restart, maxit, nu_pre, nu_post, precision, smoother, nrhs,
+                       rtol, omega)
+
+
+def xdg_create(row_ptr, col_idx, val, cell_ptr, transfers, opt, stream=None):
+    """Build a handle from host arrays (numpy); transfers: list of dicts with
+    kind, n_rows_c, np_c, parent, R, cell_ptr_c.  Returns an opaque handle."""
+    keep = []
+    rp, ci = _np(row_ptr, np.int32), _np(col_idx, np.int32)
+    v = _np(val, np.float64)
+    cp = _np(cell_ptr, np.int32)
+    keep += [rp, ci, v, cp]
+    m = xdg_matrix(len(rp) - 1, v.shape[1], len(ci), rp.ctypes.data_as(_i32p),
+                   ci.ctypes.data_as(_i32p), v.ctypes.data_as(_f64p), len(cp) - 1,
+                   cp.ctypes.data_as(_i32p))
+    T = (xdg_transfer * max(1, len(transfers)))()
+    for k, t in enumerate(transfers):
+        par = _np(t["parent"], np.int32)
+        cpc = _np(t["cell_ptr_c"], np.int32)
+        keep += [par, cpc]
+        Rp = None
+        if t["R"] is not None:
+            R = _np(t["R"], np.float64)
+            keep.append(R)
+            Rp = R.ctypes.data_as(_f64p)
+        T[k] = xdg_transfer(t["kind"], t["n_rows_c"], t["np_c"], par.ctypes.data_as(_i32p),
+                            Rp, len(cpc) - 1, cpc.ctypes.data_as(_i32p))
+    h = C.c_void_p()
+    _check(_lib.xdg_create(C.byref(m), len(transfers) + 1, T, C.byref(opt),
+                           C.c_void_p(stream or 0), C.byref(h)))
+    return h
+
+
+def xdg_spmv(h, level, x, y):
+    return _check(_lib.xdg_spmv(h, level, _ptr(x), _ptr(y)))
+
+
+def xdg_smooth(h, level, b, x, sweeps):
+    return _check(_lib.xdg_smooth(h, level, _ptr(b), _ptr(x), sweeps))
+
+
+def xdg_restrict(h, level, rf, rc):
+    return _check(_lib.xdg_restrict(h, level, _ptr(rf), _ptr(rc)))
+
+
+def xdg_prolong(h, level, xc, xf):
+    return _check(_lib.xdg_prolong(h, level, _ptr(xc), _ptr(xf)))
+
+
+def xdg_vcycle(h, r, z):
+    return _check(_lib.xdg_vcycle(h, _ptr(r), _ptr(z)))
+
+
+def xdg_solve(h, b, x, hist_cap=1000):
+    """Returns (status, iterations, final true relres, history array)."""
+    hist = np.zeros(hist_cap)
+    it = C.c_int32()
+    fr = C.c_double()
+    rc = _check(_lib.xdg_solve(h, _ptr(b), _ptr(x), hist.ctypes.data_as(_f64p), hist_cap,
+                               C.byref(it), C.byref(fr)))
+    return rc, it.value, fr.value, hist[:min(it.value + 1, hist_cap)].copy()
+
+
+def xdg_level_info(h, level):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.xdg_level_info(h, level, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def xdg_get_level_matrix(h, level):
+    n, npm, nnzb = xdg_level_info(h, level)
+    rp = np.zeros(n + 1, np.int32)
+    ci = np.zeros(nnzb, np.int32)
+    val = np.zeros((nnzb, npm, npm))
+    _check(_lib.xdg_get_level_matrix(h, level, rp.ctypes.data_as(_i32p),
+                                     ci.ctypes.data_as(_i32p), val.ctypes.data_as(_f64p)))
+    return rp, ci, val
+
+
+def xdg_get_cell_inverse(h, level, cell, cap=1 << 24):
+    out = np.zeros(cap)
+    n = C.c_int32()
+    _check(_lib.xdg_get_cell_inverse(h, level, cell, out.ctypes.data_as(_f64p), cap,
+                                     C.byref(n)))
+    return out[:n.value * n.value].reshape(n.value, n.value).copy()
+
+
+def xdg_update_matrix(h, val_dev):
+    return _check(_lib.xdg_update_matrix(h, _ptr(val_dev)))
+
+
+def xdg_setup_time(h):
+    ms = C.c_double()
+    _check(_lib.xdg_setup_time(h, C.byref(ms)))
+    return ms.value
+
+
+def xdg_destroy(h):
+    _lib.xdg_destroy(h)
+
+
+def xdg_last_error():
+    return _lib.xdg_last_error().decode()
+
+
+class Solver:
+    """Convenience owner of one handle built from a generated problem."""
+
+    def __init__(self, problem, opt=None, stream=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.opt = opt or options()
+        self.h = xdg_create(problem.row_ptr, problem.col_idx, problem.val, problem.cell_ptr,
+                            problem.transfers, self.opt, stream)
+        self.nlev = len(problem.transfers) + 1
+
+    def level_len(self, level):
+        n, npm, _ = xdg_level_info(self.h, level)
+        return n * npm
+
+    def vec(self, level=0, data=None):
+        t = self.torch
+        if data is None:
+            return t.zeros(self.level_len(level), dtype=t.float64, device=self.device)
+        return t.as_tensor(np.ascontiguousarray(data, dtype=np.float64)).to(self.device)
+
+    def close(self):
+        if self.h:
+            xdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

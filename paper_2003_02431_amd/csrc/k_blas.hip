@@ -1,0 +1,161 @@
+// FP64 vector kernels of the Krylov solvers: deterministic inner products
+// (fixed grid, fixed per-thread order, fixed tree) and fused CG updates whose
+// scalars stay in device memory.
+#include "xdg_internal.h"
+
+namespace xdg {
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+    return t;   // valid in thread 0
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ partial) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        acc += a[i] * b[i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ partial, int np,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = t;
+}
+
+// x += alpha p, r -= alpha q with alpha = scal[i_rz] / scal[i_pq]
+__global__ void k_cg_update_xr(int64_t n, const double* __restrict__ scal, int i_rz, int i_pq,
+                               const double* __restrict__ p, const double* __restrict__ q,
+                               double* __restrict__ x, double* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double alpha = scal[i_rz] / scal[i_pq];
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+}
+
+// p = z + beta p with beta = scal[i_new] / scal[i_old]
+__global__ void k_cg_update_p(int64_t n, const double* __restrict__ scal, int i_new, int i_old,
+                              const double* __restrict__ z, double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double beta = scal[i_new] / scal[i_old];
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
+__global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x,
+                             double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
+void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial,
+                double* out) {
+    k_dot_partial<<<kDotBlocks, 256, 0, s>>>(n, a, b, partial);
+    k_dot_final<<<1, 256, 0, s>>>(partial, kDotBlocks, out);
+}
+void launch_cg_update_xr(hipStream_t s, int64_t n, const double* scal, int i_rz, int i_pq,
+                         const double* p, const double* q, double* x, double* r) {
+    k_cg_update_xr<<<nblk(n, 256), 256, 0, s>>>(n, scal, i_rz, i_pq, p, q, x, r);
+}
+void launch_cg_update_p(hipStream_t s, int64_t n, const double* scal, int i_new, int i_old,
+                        const double* z, double* p) {
+    k_cg_update_p<<<nblk(n, 256), 256, 0, s>>>(n, scal, i_new, i_old, z, p);
+}
+void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
+    k_axpy<<<nblk(n, 256), 256, 0, s>>>(n, a, x, y);
+}
+void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
+    k_scale_copy<<<nblk(n, 256), 256, 0, s>>>(n, a, x, y);
+}
+
+}  // namespace xdg
+
+namespace xdg {
+
+// partial[k][blk] = sum over this block's slice of V[k] . w
+__global__ __launch_bounds__(256) void k_multidot_partial(int64_t n, int nv,
+                                                          const double* __restrict__ V,
+                                                          const double* __restrict__ w,
+                                                          double* __restrict__ partial) {
+    __shared__ double sh[4];
+    for (int k = 0; k < nv; ++k) {
+        const double* v = V + (int64_t)k * n;
+        double acc = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x)
+            acc += v[i] * w[i];
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = t;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_multidot_final(int nv, int nb,
+                                                        const double* __restrict__ partial,
+                                                        double* __restrict__ out) {
+    __shared__ double sh[4];
+    const int k = blockIdx.x;
+    if (k >= nv) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partial[(int64_t)k * nb + i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[k] = t;
+}
+
+template <bool NEG>
+__global__ void k_multi_axpy(int64_t n, int nv, const double* __restrict__ V,
+                             const double* __restrict__ coef, double* __restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < nv; ++k) acc += coef[k] * V[(int64_t)k * n + i];
+    w[i] = NEG ? w[i] - acc : w[i] + acc;
+}
+
+__global__ void k_div_scalar(int64_t n, const double* __restrict__ scal, int idx,
+                             const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] / scal[idx];
+}
+
+void launch_multidot(hipStream_t s, int64_t n, int nv, const double* V, const double* w,
+                     double* partial, double* out) {
+    k_multidot_partial<<<kDotBlocks, 256, 0, s>>>(n, nv, V, w, partial);
+    k_multidot_final<<<nv, 256, 0, s>>>(nv, kDotBlocks, partial, out);
+}
+void launch_multi_axpy_neg(hipStream_t s, int64_t n, int nv, const double* V, const double* coef,
+                           double* w) {
+    k_multi_axpy<true><<<nblk(n, 256), 256, 0, s>>>(n, nv, V, coef, w);
+}
+void launch_multi_axpy(hipStream_t s, int64_t n, int nv, const double* V, const double* coef,
+                       double* x) {
+    k_multi_axpy<false><<<nblk(n, 256), 256, 0, s>>>(n, nv, V, coef, x);
+}
+void launch_div_scalar(hipStream_t s, int64_t n, const double* scal, int i, const double* x,
+                       double* y) {
+    k_div_scalar<<<nblk(n, 256), 256, 0, s>>>(n, scal, i, x, y);
+}
+
+}  // namespace xdg

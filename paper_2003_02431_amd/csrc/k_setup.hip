@@ -1,0 +1,290 @@
+// Hierarchy set-up on the device:
+//   * block layout change (row-major input blocks -> column-major device blocks)
+//   * Galerkin coarse operators M^{lambda+1} = R^T M^lambda R (Eq. XDGsysRestriction):
+//     p-levels keep the leading np_c x np_c sub-block of every block (R_i = [I;0]);
+//     aggregation levels sum R_i^T M_il R_l over the fine blocks (i,l) that map to
+//     one coarse block, in ascending fine-block order (no atomics)
+//   * cell-block diagonal D_c gathered from the BSR and inverted in FP64 by
+//     Gauss-Jordan elimination (pivots are the Schur-complement diagonals of an
+//     SPD matrix, so no pivoting; a non-positive pivot reports "not SPD")
+//   * coarsest matrix densified and inverted by blocked Gauss-Jordan (32x32 tiles)
+#include "xdg_internal.h"
+
+namespace xdg {
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+__global__ void k_transpose_blocks(int64_t nnzb, int np, const double* __restrict__ in,
+                                   T* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb2 = (int64_t)np * np;
+    if (t >= nnzb * nb2) return;
+    const int64_t b = t / nb2;
+    const int e = (int)(t - b * nb2);
+    const int c = e / np, r = e - c * np;          // output: column-major
+    out[t] = (T)in[b * nb2 + (int64_t)r * np + c];  // input: row-major
+}
+
+__global__ void k_extract_leading(int64_t nnzb, int npf, int npc, const double* __restrict__ A,
+                                  double* __restrict__ Ac) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nc2 = (int64_t)npc * npc;
+    if (t >= nnzb * nc2) return;
+    const int64_t b = t / nc2;
+    const int e = (int)(t - b * nc2);
+    const int c = e / npc, r = e - c * npc;
+    Ac[t] = A[b * npf * npf + (int64_t)c * npf + r];
+}
+
+// one workgroup per coarse block; thread (m, m2) of the block computes
+// sum_k sum_a sum_b R_i[a][m] A_fb[a][b] R_l[b][m2]
+__global__ __launch_bounds__(64) void k_galerkin_dense(int n_cblk, int npf, int npc,
+                                                       const int* __restrict__ cptr,
+                                                       const int* __restrict__ cfb,
+                                                       const int* __restrict__ crow,
+                                                       const int* __restrict__ ccol,
+                                                       const double* __restrict__ A,
+                                                       const double* __restrict__ R,
+                                                       double* __restrict__ Ac) {
+    const int cb = blockIdx.x;
+    if (cb >= n_cblk) return;
+    const int nc2 = npc * npc;
+    for (int t = threadIdx.x; t < nc2; t += blockDim.x) {
+        const int m2 = t / npc, m = t - m2 * npc;
+        double acc = 0.0;
+        for (int k = cptr[cb]; k < cptr[cb + 1]; ++k) {
+            const double* Ab = A + (int64_t)cfb[k] * npf * npf;      // column-major
+            const double* Ri = R + (int64_t)crow[k] * npf * npc;
+            const double* Rl = R + (int64_t)ccol[k] * npf * npc;
+            for (int b = 0; b < npf; ++b) {
+                double s = 0.0;
+                for (int a = 0; a < npf; ++a) s += Ri[a * npc + m] * Ab[b * npf + a];
+                acc += s * Rl[b * npc + m2];
+            }
+        }
+        Ac[(int64_t)cb * nc2 + t] = acc;
+    }
+}
+
+// D_c (column-major n_c x n_c) from the blocks (i, l) with i, l in cell c;
+// entries not covered by a block stay at the caller's zero fill.
+__global__ __launch_bounds__(256) void k_gather_cells(int n_cells, int np,
+                                                      const int* __restrict__ cell_ptr,
+                                                      const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const double* __restrict__ A,
+                                                      const int64_t* __restrict__ doff,
+                                                      double* __restrict__ D) {
+    const int c = blockIdx.x;
+    if (c >= n_cells) return;
+    const int r0 = cell_ptr[c], r1 = cell_ptr[c + 1];
+    const int nc = (r1 - r0) * np;
+    double* Dc = D + doff[c];        // zero-filled by the caller
+    const int np2 = np * np;
+    for (int row = r0; row < r1; ++row) {
+        for (int blk = rp[row]; blk < rp[row + 1]; ++blk) {
+            const int col = ci[blk];
+            if (col < r0 || col >= r1) continue;
+            const double* Ab = A + (int64_t)blk * np2;
+            for (int e = threadIdx.x; e < np2; e += blockDim.x) {
+                const int cc = e / np, rr = e - cc * np;
+                Dc[(int64_t)((col - r0) * np + cc) * nc + (row - r0) * np + rr] = Ab[e];
+            }
+        }
+    }
+}
+
+// In-place Gauss-Jordan inverse of an n x n column-major matrix held in LDS.
+__device__ void gj_lds(double* a, int n, int* err) {
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        const double piv = a[k * n + k];
+        if (!(piv > 0.0)) {
+            if (threadIdx.x == 0) *err = 1;
+        }
+        const double ip = 1.0 / piv;
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int j = e / n, i = e - j * n;
+            if (i != k && j != k) a[e] -= a[k * n + i] * a[j * n + k] * ip;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            if (e != k) {
+                a[e * n + k] *= ip;           // row k
+                a[k * n + e] = -a[k * n + e] * ip;   // column k
+            }
+        }
+        if (threadIdx.x == 0) a[k * n + k] = ip;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_gj_batched(int n_mats, const int64_t* __restrict__ doff,
+                                                    const int* __restrict__ cell_ptr, int np,
+                                                    double* __restrict__ D, int* err) {
+    extern __shared__ double sm[];
+    const int c = blockIdx.x;
+    if (c >= n_mats) return;
+    const int n = (cell_ptr[c + 1] - cell_ptr[c]) * np;
+    double* Dc = D + doff[c];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) sm[e] = Dc[e];
+    gj_lds(sm, n, err);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) Dc[e] = sm[e];
+}
+
+// dense row-major (leading dimension ld) copy of the coarsest level, padded
+// with the identity up to npad rows
+__global__ void k_bsr_to_dense(int n_rows, int np, const int* __restrict__ rp,
+                               const int* __restrict__ ci, const double* __restrict__ A, int ld,
+                               int npad, double* __restrict__ dense) {
+    const int row = blockIdx.x;
+    const int n = n_rows * np;
+    if (row < n_rows) {
+        const int np2 = np * np;
+        for (int blk = rp[row]; blk < rp[row + 1]; ++blk) {
+            const int col = ci[blk];
+            for (int e = threadIdx.x; e < np2; e += blockDim.x) {
+                const int cc = e / np, rr = e - cc * np;
+                dense[(int64_t)(row * np + rr) * ld + col * np + cc] = A[(int64_t)blk * np2 + e];
+            }
+        }
+    } else {
+        // padding rows: identity (the single extra workgroup)
+        for (int i = n + threadIdx.x; i < npad; i += blockDim.x) dense[(int64_t)i * ld + i] = 1.0;
+    }
+}
+
+// ---- blocked Gauss-Jordan on the dense coarsest matrix (row-major) --------
+constexpr int NB = kCoarseNB;
+
+__device__ __forceinline__ void load_tile(double (*t)[NB + 1], const double* A, int ld, int I,
+                                          int J) {
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int r = e / NB, c = e - r * NB;
+        t[r][c] = A[(int64_t)(I * NB + r) * ld + J * NB + c];
+    }
+}
+
+// P = inverse of the pivot tile A_KK
+__global__ __launch_bounds__(256) void k_cgj_pivot(int K, int ld, const double* __restrict__ A,
+                                                   double* __restrict__ P, int* err) {
+    __shared__ double a[NB * NB];
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int r = e / NB, c = e - r * NB;
+        a[c * NB + r] = A[(int64_t)(K * NB + r) * ld + K * NB + c];   // column-major in LDS
+    }
+    gj_lds(a, NB, err);
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int r = e / NB, c = e - r * NB;
+        P[e] = a[c * NB + r];                                          // row-major out
+    }
+}
+
+// row K: A_KJ <- P A_KJ for J != K
+__global__ __launch_bounds__(256) void k_cgj_row(int nt, int K, int ld, double* __restrict__ A,
+                                                 const double* __restrict__ P) {
+    __shared__ double p[NB][NB + 1], t[NB][NB + 1];
+    const int J = blockIdx.x + (blockIdx.x >= (unsigned)K ? 1 : 0);
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = P[e];
+    load_tile(t, A, ld, K, J);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int r = e / NB, c = e - r * NB;
+        double s = 0.0;
+        for (int k = 0; k < NB; ++k) s += p[r][k] * t[k][c];
+        A[(int64_t)(K * NB + r) * ld + J * NB + c] = s;
+    }
+}
+
+// A_IJ <- A_IJ - A_IK A_KJ for I, J != K (row K already updated)
+__global__ __launch_bounds__(256) void k_cgj_update(int nt, int K, int ld, double* __restrict__ A) {
+    __shared__ double u[NB][NB + 1], v[NB][NB + 1];
+    const int m = nt - 1;
+    const int Ip = blockIdx.x / m, Jp = blockIdx.x - Ip * m;
+    const int I = Ip + (Ip >= K ? 1 : 0), J = Jp + (Jp >= K ? 1 : 0);
+    load_tile(u, A, ld, I, K);
+    load_tile(v, A, ld, K, J);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int r = e / NB, c = e - r * NB;
+        double s = 0.0;
+        for (int k = 0; k < NB; ++k) s += u[r][k] * v[k][c];
+        A[(int64_t)(I * NB + r) * ld + J * NB + c] -= s;
+    }
+}
+
+// column K: A_IK <- -A_IK P for I != K ; A_KK <- P
+__global__ __launch_bounds__(256) void k_cgj_col(int nt, int K, int ld, double* __restrict__ A,
+                                                 const double* __restrict__ P) {
+    __shared__ double p[NB][NB + 1], t[NB][NB + 1];
+    const int I = blockIdx.x;
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = P[e];
+    if (I == K) {
+        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
+            A[(int64_t)(K * NB + e / NB) * ld + K * NB + e % NB] = P[e];
+        return;
+    }
+    load_tile(t, A, ld, I, K);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int r = e / NB, c = e - r * NB;
+        double s = 0.0;
+        for (int k = 0; k < NB; ++k) s += t[r][k] * p[k][c];
+        A[(int64_t)(I * NB + r) * ld + K * NB + c] = -s;
+    }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(int64_t n, const Tin* __restrict__ in, Tout* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (Tout)in[t];
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* in, T* out) {
+    const int64_t n = nnzb * np * np;
+    k_transpose_blocks<T><<<nblk(n, 256), 256, 0, s>>>(nnzb, np, in, out);
+}
+void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const double* A,
+                            double* Ac) {
+    k_extract_leading<<<nblk(nnzb * npc * npc, 256), 256, 0, s>>>(nnzb, npf, npc, A, Ac);
+}
+void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
+                           const int* cfb, const int* crow, const int* ccol, const double* A,
+                           const double* R, double* Ac) {
+    k_galerkin_dense<<<n_cblk, 64, 0, s>>>(n_cblk, npf, npc, cptr, cfb, crow, ccol, A, R, Ac);
+}
+void launch_gather_cells(hipStream_t s, int n_cells, int np, const int* cell_ptr, const int* rp,
+                         const int* ci, const double* A, const int64_t* doff, double* D) {
+    k_gather_cells<<<n_cells, 256, 0, s>>>(n_cells, np, cell_ptr, rp, ci, A, doff, D);
+}
+void launch_gj_batched(hipStream_t s, int n_mats, const int64_t* doff, const int* cell_ptr,
+                       int np, int max_n, double* D, int* err) {
+    const size_t lds = (size_t)max_n * max_n * sizeof(double);
+    k_gj_batched<<<n_mats, 256, lds, s>>>(n_mats, doff, cell_ptr, np, D, err);
+}
+void launch_bsr_to_dense(hipStream_t s, int n_rows, int np, const int* rp, const int* ci,
+                         const double* A, int ld, int npad, double* dense) {
+    k_bsr_to_dense<<<n_rows + 1, 256, 0, s>>>(n_rows, np, rp, ci, A, ld, npad, dense);
+}
+void launch_coarse_gj_step(hipStream_t s, int nt, int K, int ld, double* A, double* P, int* err) {
+    k_cgj_pivot<<<1, 256, 0, s>>>(K, ld, A, P, err);
+    if (nt > 1) {
+        k_cgj_row<<<nt - 1, 256, 0, s>>>(nt, K, ld, A, P);
+        k_cgj_update<<<(nt - 1) * (nt - 1), 256, 0, s>>>(nt, K, ld, A);
+    }
+    k_cgj_col<<<nt, 256, 0, s>>>(nt, K, ld, A, P);
+}
+template <typename Tin, typename Tout>
+void launch_convert(hipStream_t s, int64_t n, const Tin* in, Tout* out) {
+    k_convert<Tin, Tout><<<nblk(n, 256), 256, 0, s>>>(n, in, out);
+}
+
+template void launch_transpose_blocks<double>(hipStream_t, int64_t, int, const double*, double*);
+template void launch_transpose_blocks<float>(hipStream_t, int64_t, int, const double*, float*);
+template void launch_convert<double, float>(hipStream_t, int64_t, const double*, float*);
+template void launch_convert<float, double>(hipStream_t, int64_t, const float*, double*);
+
+}  // namespace xdg

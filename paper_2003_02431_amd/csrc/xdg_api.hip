@@ -1,0 +1,893 @@
+// C-ABI of libxdg: hierarchy construction and the solver loops (host side).
+// Every arithmetic step runs in the kernels of k_level.hip / k_setup.hip /
+// k_blas.hip; this file only validates input, does the integer bookkeeping of
+// the Galerkin sparsity pattern, and sequences launches on the handle's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "xdg.h"
+#include "xdg_internal.h"
+
+using namespace xdg;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                           \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess)                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? XDG_ENOMEM : XDG_EHIP,                  \
+                        std::string(#x) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+#define CHK(x)                      \
+    do {                            \
+        int rc_ = (x);              \
+        if (rc_ < 0) return rc_;    \
+    } while (0)
+
+namespace {
+
+struct Level {
+    int n_rows = 0, np = 0, nnzb = 0, n_cells = 0, max_nc = 0;
+    std::vector<int> h_rp, h_ci, h_cp;
+    int *rp = nullptr, *ci = nullptr, *cp = nullptr;
+    double* A64 = nullptr;
+    float* A32 = nullptr;
+    int64_t* doff = nullptr;
+    int64_t dsize = 0;
+    std::vector<int64_t> h_doff;
+    double* D64 = nullptr;
+    float* D32 = nullptr;
+    // Galerkin contributions forming the next coarser level (dense transfers)
+    int *g_ptr = nullptr, *g_fb = nullptr, *g_row = nullptr, *g_col = nullptr;
+    // transfer to the next coarser level
+    int t_kind = -1, npc = 0, n_c = 0;
+    int *parent = nullptr, *chp = nullptr, *chi = nullptr;
+    double* R64 = nullptr;
+    float* R32 = nullptr;
+    // work vectors
+    double *b64 = nullptr, *x64 = nullptr, *y64 = nullptr, *r64 = nullptr;
+    float *b32 = nullptr, *x32 = nullptr, *y32 = nullptr, *r32 = nullptr;
+    int64_t len() const { return (int64_t)n_rows * np; }
+};
+
+template <typename T> struct P;
+template <> struct P<double> {
+    static double* A(Level& l) { return l.A64; }
+    static double* D(Level& l) { return l.D64; }
+    static double* R(Level& l) { return l.R64; }
+    static double*& b(Level& l) { return l.b64; }
+    static double*& x(Level& l) { return l.x64; }
+    static double*& y(Level& l) { return l.y64; }
+    static double*& r(Level& l) { return l.r64; }
+};
+template <> struct P<float> {
+    static float* A(Level& l) { return l.A32; }
+    static float* D(Level& l) { return l.D32; }
+    static float* R(Level& l) { return l.R32; }
+    static float*& b(Level& l) { return l.b32; }
+    static float*& x(Level& l) { return l.x32; }
+    static float*& y(Level& l) { return l.y32; }
+    static float*& r(Level& l) { return l.r32; }
+};
+
+}  // namespace
+
+struct xdg_handle {
+    hipStream_t s = nullptr;
+    xdg_options opt{};
+    std::vector<Level> L;
+    int cn = 0, cld = 0;            // coarsest order, padded leading dimension
+    double* Cinv = nullptr;
+    double* Pbuf = nullptr;         // pivot tile of the coarse inversion
+    double* scal = nullptr;         // device scalars
+    double* part = nullptr;         // reduction partials
+    double* h_scal = nullptr;       // pinned host mirror
+    int* d_err = nullptr;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr;
+    double *V = nullptr, *Z = nullptr;
+    std::vector<void*> allocs;
+    double setup_ms = 0.0;
+    bool mixed = false;
+
+    template <typename T>
+    int alloc(T** ptr, size_t n) {
+        *ptr = nullptr;
+        if (n == 0) n = 1;
+        hipError_t e = hipMalloc((void**)ptr, n * sizeof(T));
+        if (e != hipSuccess) {
+            *ptr = nullptr;
+            return fail(e == hipErrorOutOfMemory ? XDG_ENOMEM : XDG_EHIP,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        allocs.push_back((void*)*ptr);
+        return XDG_OK;
+    }
+    template <typename T>
+    int upload(T** ptr, const T* host, size_t n) {
+        CHK(alloc(ptr, n));
+        HIPCHK(hipMemcpyAsync(*ptr, host, n * sizeof(T), hipMemcpyHostToDevice, s));
+        return XDG_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// validation
+
+static int check_pattern(int n_rows, int nnzb, const int32_t* rp, const int32_t* ci,
+                         const char* what) {
+    if (!rp || !ci) return fail(XDG_EINVAL, std::string(what) + ": NULL row_ptr/col_idx");
+    if (rp[0] != 0 || rp[n_rows] != nnzb)
+        return fail(XDG_EINVAL, std::string(what) + ": row_ptr does not span [0, nnzb]");
+    for (int i = 0; i < n_rows; ++i) {
+        if (rp[i + 1] <= rp[i]) return fail(XDG_EINVAL, std::string(what) + ": empty block row");
+        bool diag = false;
+        for (int b = rp[i]; b < rp[i + 1]; ++b) {
+            if (ci[b] < 0 || ci[b] >= n_rows)
+                return fail(XDG_EINVAL, std::string(what) + ": column index out of range");
+            if (b > rp[i] && ci[b] <= ci[b - 1])
+                return fail(XDG_EINVAL, std::string(what) + ": columns not strictly sorted");
+            diag |= ci[b] == i;
+        }
+        if (!diag) return fail(XDG_EINVAL, std::string(what) + ": missing diagonal block");
+    }
+    return XDG_OK;
+}
+
+static int check_cells(int n_rows, int np, int n_cells, const int32_t* cp, const char* what) {
+    if (n_cells < 1 || !cp) return fail(XDG_EINVAL, std::string(what) + ": no cell blocks");
+    if (cp[0] != 0 || cp[n_cells] != n_rows)
+        return fail(XDG_EINVAL, std::string(what) + ": cell_ptr does not span the rows");
+    for (int c = 0; c < n_cells; ++c) {
+        if (cp[c + 1] <= cp[c]) return fail(XDG_EINVAL, std::string(what) + ": empty cell block");
+        if ((int64_t)(cp[c + 1] - cp[c]) * np > kMaxCell)
+            return fail(XDG_EINVAL, std::string(what) + ": cell block larger than " +
+                                        std::to_string(kMaxCell));
+    }
+    return XDG_OK;
+}
+
+static bool finite_all(const double* v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// set-up helpers
+
+static int setup_cells(xdg_handle* h, Level& lv, const int32_t* cp, int n_cells) {
+    lv.n_cells = n_cells;
+    lv.h_cp.assign(cp, cp + n_cells + 1);
+    lv.h_doff.resize(n_cells + 1);
+    int64_t off = 0;
+    lv.max_nc = 0;
+    for (int c = 0; c < n_cells; ++c) {
+        const int nc = (cp[c + 1] - cp[c]) * lv.np;
+        lv.h_doff[c] = off;
+        off += (int64_t)nc * nc;
+        lv.max_nc = std::max(lv.max_nc, nc);
+    }
+    lv.h_doff[n_cells] = off;
+    lv.dsize = off;
+    CHK(h->upload(&lv.cp, lv.h_cp.data(), lv.h_cp.size()));
+    CHK(h->upload(&lv.doff, lv.h_doff.data(), lv.h_doff.size()));
+    return XDG_OK;
+}
+
+static int setup_vectors(xdg_handle* h, Level& lv, bool mixed) {
+    const int64_t n = lv.len();
+    CHK(h->alloc(&lv.b64, n));
+    CHK(h->alloc(&lv.x64, n));
+    CHK(h->alloc(&lv.y64, n));
+    CHK(h->alloc(&lv.r64, n));
+    if (mixed) {
+        CHK(h->alloc(&lv.b32, n));
+        CHK(h->alloc(&lv.x32, n));
+        CHK(h->alloc(&lv.y32, n));
+        CHK(h->alloc(&lv.r32, n));
+    }
+    return XDG_OK;
+}
+
+// Galerkin level l -> l+1 for a dense transfer: the integer pattern and the
+// list of fine blocks contributing to every coarse block (ascending fine-block
+// order) are built once on the host; the products run in numeric_setup.
+static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* parent) {
+    const int nf = f.n_rows, ncr = c.n_rows;
+    struct Item { int64_t key; int fb, i, l; };
+    std::vector<Item> it;
+    it.reserve(f.nnzb);
+    for (int i = 0; i < nf; ++i)
+        for (int b = f.h_rp[i]; b < f.h_rp[i + 1]; ++b) {
+            const int l = f.h_ci[b];
+            it.push_back({(int64_t)parent[i] * ncr + parent[l], b, i, l});
+        }
+    std::stable_sort(it.begin(), it.end(), [](const Item& a, const Item& b) { return a.key < b.key; });
+    std::vector<int> cptr, cfb(it.size()), crow(it.size()), ccol(it.size());
+    c.h_rp.assign(ncr + 1, 0);
+    c.h_ci.clear();
+    for (size_t k = 0; k < it.size(); ++k) {
+        if (k == 0 || it[k].key != it[k - 1].key) {
+            cptr.push_back((int)k);
+            const int row = (int)(it[k].key / ncr), col = (int)(it[k].key % ncr);
+            c.h_ci.push_back(col);
+            c.h_rp[row + 1]++;
+        }
+        cfb[k] = it[k].fb;
+        crow[k] = it[k].i;
+        ccol[k] = it[k].l;
+    }
+    cptr.push_back((int)it.size());
+    for (int i = 0; i < ncr; ++i) c.h_rp[i + 1] += c.h_rp[i];
+    c.nnzb = (int)c.h_ci.size();
+    CHK(check_pattern(ncr, c.nnzb, c.h_rp.data(), c.h_ci.data(), "coarse level"));
+    CHK(h->upload(&c.rp, c.h_rp.data(), c.h_rp.size()));
+    CHK(h->upload(&c.ci, c.h_ci.data(), c.h_ci.size()));
+    CHK(h->upload(&f.g_ptr, cptr.data(), cptr.size()));
+    CHK(h->upload(&f.g_fb, cfb.data(), cfb.size()));
+    CHK(h->upload(&f.g_row, crow.data(), crow.size()));
+    CHK(h->upload(&f.g_col, ccol.data(), ccol.size()));
+    CHK(h->alloc(&c.A64, (size_t)c.nnzb * c.np * c.np));
+    return XDG_OK;
+}
+
+static int invert_cells(xdg_handle* h, Level& lv) {
+    HIPCHK(hipMemsetAsync(lv.D64, 0, lv.dsize * sizeof(double), h->s));
+    launch_gather_cells(h->s, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff, lv.D64);
+    launch_gj_batched(h->s, lv.n_cells, lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64, h->d_err);
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+static int invert_coarsest(xdg_handle* h, Level& lv) {
+    const int nt = h->cld / kCoarseNB;
+    HIPCHK(hipMemsetAsync(h->Cinv, 0, (size_t)h->cld * h->cld * sizeof(double), h->s));
+    launch_bsr_to_dense(h->s, lv.n_rows, lv.np, lv.rp, lv.ci, lv.A64, h->cld, h->cld, h->Cinv);
+    for (int K = 0; K < nt; ++K)
+        launch_coarse_gj_step(h->s, nt, K, h->cld, h->Cinv, h->Pbuf, h->d_err);
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+// Numeric phase of the set-up from level-0 values `raw` (device, row-major
+// blocks): layout change, Galerkin chain, cell-block and coarsest inverses,
+// FP32 copies.  Errors of the inversions are reported through d_err.
+static int numeric_setup(xdg_handle* h, const double* raw) {
+    hipStream_t s = h->s;
+    const int nl = (int)h->L.size();
+    HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), s));
+    Level& L0 = h->L[0];
+    launch_transpose_blocks<double>(s, L0.nnzb, L0.np, raw, L0.A64);
+    for (int t = 0; t + 1 < nl; ++t) {
+        Level& f = h->L[t];
+        Level& c = h->L[t + 1];
+        if (f.t_kind == XDG_T_PTRUNC)
+            launch_extract_leading(s, f.nnzb, f.np, c.np, f.A64, c.A64);
+        else
+            launch_galerkin_dense(s, c.nnzb, f.np, c.np, f.g_ptr, f.g_fb, f.g_row, f.g_col,
+                                  f.A64, f.R64, c.A64);
+    }
+    for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l]));
+    CHK(invert_coarsest(h, h->L[nl - 1]));
+    if (h->mixed) {
+        for (int l = 0; l + 1 < nl; ++l) {
+            Level& lv = h->L[l];
+            launch_convert<double, float>(s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
+            launch_convert<double, float>(s, lv.dsize, lv.D64, lv.D32);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+static int check_setup_error(xdg_handle* h) {
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    if (herr) return fail(XDG_ENOTSPD, "non-positive pivot in a cell block or the coarsest "
+                                       "matrix (not SPD)");
+    return XDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (templated on the storage precision of levels above the coarsest)
+
+template <typename T>
+static void smooth_from_zero(xdg_handle* h, Level& lv, int sweeps) {
+    T* b = P<T>::b(lv);
+    T*& x = P<T>::x(lv);
+    T*& y = P<T>::y(lv);
+    const T om = (T)h->opt.omega;
+    if (sweeps <= 0) {
+        (void)hipMemsetAsync(x, 0, lv.len() * sizeof(T), h->s);
+        return;
+    }
+    launch_jacobi<T>(h->s, true, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv), lv.doff,
+                     P<T>::D(lv), b, nullptr, x, om);
+    for (int k = 1; k < sweeps; ++k) {
+        launch_jacobi<T>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv),
+                         lv.doff, P<T>::D(lv), b, x, y, om);
+        std::swap(x, y);
+    }
+}
+
+template <typename T>
+static void smooth_more(xdg_handle* h, Level& lv, int sweeps) {
+    T* b = P<T>::b(lv);
+    T*& x = P<T>::x(lv);
+    T*& y = P<T>::y(lv);
+    for (int k = 0; k < sweeps; ++k) {
+        launch_jacobi<T>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv),
+                         lv.doff, P<T>::D(lv), b, x, y, (T)h->opt.omega);
+        std::swap(x, y);
+    }
+}
+
+template <typename T>
+static void coarse_solve(xdg_handle* h, Level& lv);
+
+template <>
+void coarse_solve<double>(xdg_handle* h, Level& lv) {
+    launch_coarse_gemv(h->s, h->cn, h->cld, h->Cinv, lv.b64, lv.x64);
+}
+template <>
+void coarse_solve<float>(xdg_handle* h, Level& lv) {
+    launch_convert<float, double>(h->s, lv.len(), lv.b32, lv.b64);
+    launch_coarse_gemv(h->s, h->cn, h->cld, h->Cinv, lv.b64, lv.x64);
+    launch_convert<double, float>(h->s, lv.len(), lv.x64, lv.x32);
+}
+
+// input: P<T>::b(L[l]); output: P<T>::x(L[l])
+template <typename T>
+static void vcycle(xdg_handle* h, int l) {
+    Level& f = h->L[l];
+    if (l == (int)h->L.size() - 1) {
+        coarse_solve<T>(h, f);
+        return;
+    }
+    Level& c = h->L[l + 1];
+    smooth_from_zero<T>(h, f, h->opt.nu_pre);
+    if (f.t_kind == XDG_T_PTRUNC) {
+        launch_spmv<T>(h->s, SPMV_RESID_TRUNC, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f),
+                       P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np);
+    } else {
+        launch_spmv<T>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f), P<T>::x(f),
+                       P<T>::b(f), P<T>::r(f), 0);
+        launch_restrict_dense<T>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, P<T>::R(f),
+                                 P<T>::r(f), P<T>::b(c));
+    }
+    vcycle<T>(h, l + 1);
+    if (f.t_kind == XDG_T_PTRUNC)
+        launch_prolong_trunc<T>(h->s, f.n_rows, f.np, c.np, P<T>::x(c), P<T>::x(f));
+    else
+        launch_prolong_dense<T>(h->s, f.n_rows, f.np, c.np, f.parent, P<T>::R(f), P<T>::x(c),
+                                P<T>::x(f));
+    smooth_more<T>(h, f, h->opt.nu_post);
+}
+
+// z = B r for FP64 vectors, using the handle's precision for the cycle
+static int apply_precond(xdg_handle* h, const double* r, double* z) {
+    Level& f = h->L[0];
+    const int64_t n = f.len();
+    if (h->mixed) {
+        launch_convert<double, float>(h->s, n, r, f.b32);
+        vcycle<float>(h, 0);
+        launch_convert<float, double>(h->s, n, f.x32, z);
+    } else {
+        HIPCHK(hipMemcpyAsync(f.b64, r, n * sizeof(double), hipMemcpyDeviceToDevice, h->s));
+        vcycle<double>(h, 0);
+        HIPCHK(hipMemcpyAsync(z, f.x64, n * sizeof(double), hipMemcpyDeviceToDevice, h->s));
+    }
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// public API
+
+extern "C" const char* xdg_last_error(void) { return g_err.c_str(); }
+
+extern "C" void xdg_destroy(xdg_handle* h) {
+    if (!h) return;
+    if (h->s) (void)hipStreamSynchronize(h->s);
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->h_scal) (void)hipHostFree(h->h_scal);
+    delete h;
+}
+
+static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
+                       const xdg_transfer* T, const xdg_options* opt) {
+    // -- validation -----------------------------------------------------
+    if (!A0 || !opt || n_levels < 1 || (n_levels > 1 && !T))
+        return fail(XDG_EINVAL, "xdg_create: NULL argument or n_levels < 1");
+    if (A0->n_rows < 1 || A0->np < 1 || A0->np > 64 || A0->nnzb < A0->n_rows || !A0->val)
+        return fail(XDG_EINVAL, "xdg_create: bad matrix sizes");
+    CHK(check_pattern(A0->n_rows, A0->nnzb, A0->row_ptr, A0->col_idx, "level-0 matrix"));
+    CHK(check_cells(A0->n_rows, A0->np, A0->n_cells, A0->cell_ptr, "level-0 cells"));
+    if (!finite_all(A0->val, (size_t)A0->nnzb * A0->np * A0->np))
+        return fail(XDG_EINVAL, "xdg_create: non-finite matrix entry");
+    if (!(opt->omega > 0.0 && opt->omega < 2.0) || opt->nu_pre < 0 || opt->nu_post < 0 ||
+        opt->maxit < 1 || !(opt->rtol > 0.0) || opt->nrhs != 1 ||
+        (opt->krylov != XDG_CG && opt->krylov != XDG_FGMRES) ||
+        (opt->precision != XDG_FP64 && opt->precision != XDG_MIXED) ||
+        opt->smoother != XDG_JACOBI)
+        return fail(XDG_EINVAL, "xdg_create: invalid options");
+    if (opt->krylov == XDG_FGMRES && (opt->restart < 1 || opt->restart > 64))
+        return fail(XDG_EINVAL, "xdg_create: FGMRES restart must be in [1, 64]");
+    if (opt->krylov == XDG_CG && opt->precision != XDG_FP64)
+        return fail(XDG_EINVAL, "xdg_create: CG needs the FP64 (symmetric) preconditioner");
+    if (opt->krylov == XDG_CG && opt->nu_pre != opt->nu_post)
+        return fail(XDG_EINVAL, "xdg_create: CG needs nu_pre == nu_post (symmetric V-cycle)");
+    int nr = A0->n_rows, npf = A0->np;
+    for (int t = 0; t < n_levels - 1; ++t) {
+        const xdg_transfer& tr = T[t];
+        const std::string w = "transfer " + std::to_string(t);
+        if (tr.np_c < 1 || tr.np_c > 64 || tr.n_rows_c < 1)
+            return fail(XDG_EINVAL, w + ": bad coarse sizes");
+        if (tr.kind == XDG_T_PTRUNC) {
+            if (tr.np_c > npf || tr.n_rows_c != nr)
+                return fail(XDG_EINVAL, w + ": p-truncation needs np_c <= np_f, same rows");
+        } else if (tr.kind == XDG_T_DENSE) {
+            if (!tr.parent || !tr.R) return fail(XDG_EINVAL, w + ": NULL parent/R");
+            std::vector<int> cnt(tr.n_rows_c, 0);
+            for (int i = 0; i < nr; ++i) {
+                if (tr.parent[i] < 0 || tr.parent[i] >= tr.n_rows_c)
+                    return fail(XDG_EINVAL, w + ": parent out of range");
+                cnt[tr.parent[i]]++;
+            }
+            for (int c = 0; c < tr.n_rows_c; ++c)
+                if (!cnt[c]) return fail(XDG_EINVAL, w + ": coarse row without children");
+            if (!finite_all(tr.R, (size_t)nr * npf * tr.np_c))
+                return fail(XDG_EINVAL, w + ": non-finite R");
+        } else {
+            return fail(XDG_EINVAL, w + ": unknown kind");
+        }
+        CHK(check_cells(tr.n_rows_c, tr.np_c, tr.n_cells_c, tr.cell_ptr_c,
+                        (w + " coarse cells").c_str()));
+        nr = tr.n_rows_c;
+        npf = tr.np_c;
+    }
+    if ((int64_t)nr * npf > 16384)
+        return fail(XDG_EINVAL, "xdg_create: coarsest level too large for the dense solve");
+
+    h->opt = *opt;
+    h->mixed = opt->precision == XDG_MIXED;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    CHK(h->alloc(&h->d_err, 1));
+
+    // -- symbolic phase: patterns, transfers, allocations ----------------------
+    h->L.resize(n_levels);
+    Level& L0 = h->L[0];
+    L0.n_rows = A0->n_rows;
+    L0.np = A0->np;
+    L0.nnzb = A0->nnzb;
+    L0.h_rp.assign(A0->row_ptr, A0->row_ptr + L0.n_rows + 1);
+    L0.h_ci.assign(A0->col_idx, A0->col_idx + L0.nnzb);
+    CHK(h->upload(&L0.rp, L0.h_rp.data(), L0.h_rp.size()));
+    CHK(h->upload(&L0.ci, L0.h_ci.data(), L0.h_ci.size()));
+    CHK(h->alloc(&L0.A64, (size_t)L0.nnzb * L0.np * L0.np));
+    CHK(setup_cells(h, L0, A0->cell_ptr, A0->n_cells));
+    for (int t = 0; t < n_levels - 1; ++t) {
+        Level& f = h->L[t];
+        Level& c = h->L[t + 1];
+        const xdg_transfer& tr = T[t];
+        f.t_kind = tr.kind;
+        f.npc = tr.np_c;
+        f.n_c = tr.n_rows_c;
+        c.n_rows = tr.n_rows_c;
+        c.np = tr.np_c;
+        if (tr.kind == XDG_T_PTRUNC) {
+            c.nnzb = f.nnzb;
+            c.h_rp = f.h_rp;
+            c.h_ci = f.h_ci;
+            CHK(h->upload(&c.rp, c.h_rp.data(), c.h_rp.size()));
+            CHK(h->upload(&c.ci, c.h_ci.data(), c.h_ci.size()));
+            CHK(h->alloc(&c.A64, (size_t)c.nnzb * c.np * c.np));
+        } else {
+            CHK(h->upload(&f.parent, tr.parent, f.n_rows));
+            CHK(h->upload(&f.R64, tr.R, (size_t)f.n_rows * f.np * c.np));
+            // children lists (ascending fine index)
+            std::vector<int> chp(c.n_rows + 1, 0), chi(f.n_rows);
+            for (int i = 0; i < f.n_rows; ++i) chp[tr.parent[i] + 1]++;
+            for (int k = 0; k < c.n_rows; ++k) chp[k + 1] += chp[k];
+            std::vector<int> fill(chp.begin(), chp.end() - 1);
+            for (int i = 0; i < f.n_rows; ++i) chi[fill[tr.parent[i]]++] = i;
+            CHK(h->upload(&f.chp, chp.data(), chp.size()));
+            CHK(h->upload(&f.chi, chi.data(), chi.size()));
+            CHK(galerkin_symbolic(h, f, c, tr.parent));
+            if (h->mixed) {
+                const int64_t nrr = (int64_t)f.n_rows * f.np * c.np;
+                CHK(h->alloc(&f.R32, nrr));
+                launch_convert<double, float>(h->s, nrr, f.R64, f.R32);
+            }
+        }
+        CHK(setup_cells(h, c, tr.cell_ptr_c, tr.n_cells_c));
+    }
+    for (int l = 0; l + 1 < n_levels; ++l) {
+        Level& lv = h->L[l];
+        CHK(h->alloc(&lv.D64, lv.dsize));
+        if (h->mixed) {
+            CHK(h->alloc(&lv.A32, (size_t)lv.nnzb * lv.np * lv.np));
+            CHK(h->alloc(&lv.D32, lv.dsize));
+        }
+    }
+    {
+        Level& lc = h->L[n_levels - 1];
+        h->cn = lc.n_rows * lc.np;
+        h->cld = ((h->cn + kCoarseNB - 1) / kCoarseNB) * kCoarseNB;
+        CHK(h->alloc(&h->Cinv, (size_t)h->cld * h->cld));
+        CHK(h->alloc(&h->Pbuf, kCoarseNB * kCoarseNB));
+    }
+    for (auto& lv : h->L) CHK(setup_vectors(h, lv, h->mixed));
+    const int64_t n0 = L0.len();
+    CHK(h->alloc(&h->scal, 256));
+    CHK(h->alloc(&h->part, (size_t)kDotBlocks * 72));
+    HIPCHK(hipHostMalloc((void**)&h->h_scal, 256 * sizeof(double), hipHostMallocDefault));
+    CHK(h->alloc(&h->r, n0));
+    CHK(h->alloc(&h->z, n0));
+    CHK(h->alloc(&h->p, n0));
+    CHK(h->alloc(&h->q, n0));
+    CHK(h->alloc(&h->w, n0));
+    if (opt->krylov == XDG_FGMRES) {
+        CHK(h->alloc(&h->V, (size_t)(opt->restart + 1) * n0));
+        CHK(h->alloc(&h->Z, (size_t)opt->restart * n0));
+    }
+
+    // -- numeric phase ------------------------------------------------------
+    {
+        const size_t nv = (size_t)L0.nnzb * L0.np * L0.np;
+        double* raw;
+        CHK(h->upload(&raw, A0->val, nv));
+        HIPCHK(hipEventRecord(e0, h->s));
+        CHK(numeric_setup(h, raw));
+        HIPCHK(hipEventRecord(e1, h->s));
+        HIPCHK(hipEventSynchronize(e1));
+        h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), (void*)raw));
+        HIPCHK(hipFree(raw));
+    }
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    h->setup_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    CHK(check_setup_error(h));
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+extern "C" int xdg_create(const xdg_matrix* A0, int32_t n_levels, const xdg_transfer* T,
+                          const xdg_options* opt, void* hip_stream, xdg_handle** out) {
+    if (!out) return fail(XDG_EINVAL, "xdg_create: out is NULL");
+    *out = nullptr;
+    xdg_handle* h = new xdg_handle();
+    h->s = (hipStream_t)hip_stream;
+    const int rc = create_impl(h, A0, n_levels, T, opt);
+    if (rc < 0) {
+        const std::string msg = g_err;
+        xdg_destroy(h);
+        g_err = msg;
+        return rc;
+    }
+    *out = h;
+    return XDG_OK;
+}
+
+static int check_level(xdg_handle* h, int level, bool need_transfer) {
+    if (!h) return fail(XDG_EINVAL, "NULL handle");
+    const int nl = (int)h->L.size();
+    if (level < 0 || level >= nl - (need_transfer ? 1 : 0))
+        return fail(XDG_EINVAL, "level out of range");
+    return XDG_OK;
+}
+
+extern "C" int xdg_level_info(xdg_handle* h, int32_t level, int32_t* n_rows, int32_t* np,
+                              int32_t* nnzb) {
+    CHK(check_level(h, level, false));
+    const Level& lv = h->L[level];
+    if (n_rows) *n_rows = lv.n_rows;
+    if (np) *np = lv.np;
+    if (nnzb) *nnzb = lv.nnzb;
+    return XDG_OK;
+}
+
+extern "C" int xdg_spmv(xdg_handle* h, int32_t level, const double* x, double* y) {
+    CHK(check_level(h, level, false));
+    if (!x || !y) return fail(XDG_EINVAL, "xdg_spmv: NULL vector");
+    Level& lv = h->L[level];
+    launch_spmv<double>(h->s, SPMV_AX, lv.n_rows, lv.np, lv.rp, lv.ci, lv.A64, x, nullptr, y, 0);
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+extern "C" int xdg_smooth(xdg_handle* h, int32_t level, const double* b, double* x,
+                          int32_t sweeps) {
+    CHK(check_level(h, level, true));
+    if (!b || !x || sweeps < 0) return fail(XDG_EINVAL, "xdg_smooth: bad argument");
+    Level& lv = h->L[level];
+    for (int k = 0; k < sweeps; ++k) {
+        launch_jacobi<double>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64,
+                              lv.doff, lv.D64, b, x, lv.y64, h->opt.omega);
+        HIPCHK(hipMemcpyAsync(x, lv.y64, lv.len() * sizeof(double), hipMemcpyDeviceToDevice,
+                              h->s));
+    }
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+extern "C" int xdg_restrict(xdg_handle* h, int32_t level, const double* rf, double* rc) {
+    CHK(check_level(h, level, true));
+    if (!rf || !rc) return fail(XDG_EINVAL, "xdg_restrict: NULL vector");
+    Level& f = h->L[level];
+    Level& c = h->L[level + 1];
+    if (f.t_kind == XDG_T_PTRUNC)
+        launch_restrict_trunc<double>(h->s, f.n_rows, f.np, c.np, rf, rc);
+    else
+        launch_restrict_dense<double>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.R64, rf, rc);
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+extern "C" int xdg_prolong(xdg_handle* h, int32_t level, const double* xc, double* xf) {
+    CHK(check_level(h, level, true));
+    if (!xc || !xf) return fail(XDG_EINVAL, "xdg_prolong: NULL vector");
+    Level& f = h->L[level];
+    Level& c = h->L[level + 1];
+    if (f.t_kind == XDG_T_PTRUNC)
+        launch_prolong_trunc<double>(h->s, f.n_rows, f.np, c.np, xc, xf);
+    else
+        launch_prolong_dense<double>(h->s, f.n_rows, f.np, c.np, f.parent, f.R64, xc, xf);
+    HIPCHK(hipGetLastError());
+    return XDG_OK;
+}
+
+extern "C" int xdg_vcycle(xdg_handle* h, const double* r, double* z) {
+    if (!h || !r || !z) return fail(XDG_EINVAL, "xdg_vcycle: NULL argument");
+    return apply_precond(h, r, z);
+}
+
+// -- Krylov solvers -------------------------------------------------------------
+
+enum { S_BB = 0, S_RR = 1, S_PQ = 2, S_RZ0 = 3, S_RZ1 = 4, S_H = 8 };
+
+static int read_scalars(xdg_handle* h, int first, int count) {
+    HIPCHK(hipMemcpyAsync(h->h_scal + first, h->scal + first, count * sizeof(double),
+                          hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return XDG_OK;
+}
+
+static int true_relres(xdg_handle* h, const double* b, const double* x, double* out) {
+    Level& f = h->L[0];
+    launch_spmv<double>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->w, 0);
+    launch_dot(h->s, f.len(), h->w, h->w, h->part, h->scal + S_RR);
+    launch_dot(h->s, f.len(), b, b, h->part, h->scal + S_BB);
+    CHK(read_scalars(h, S_BB, 2));
+    *out = std::sqrt(h->h_scal[S_RR]) / std::sqrt(h->h_scal[S_BB]);
+    return XDG_OK;
+}
+
+static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int cap,
+                    int* iters) {
+    Level& f = h->L[0];
+    const int64_t n = f.len();
+    hipStream_t s = h->s;
+    launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0);
+    launch_dot(s, n, b, b, h->part, h->scal + S_BB);
+    launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
+    CHK(read_scalars(h, S_BB, 2));
+    const double nb = std::sqrt(h->h_scal[S_BB]);
+    if (nb == 0.0) {
+        HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+        *iters = 0;
+        if (cap > 0) hist[0] = 0.0;
+        return XDG_OK;
+    }
+    double rel = std::sqrt(h->h_scal[S_RR]) / nb;
+    if (cap > 0) hist[0] = rel;
+    *iters = 0;
+    if (rel <= h->opt.rtol) return XDG_OK;
+    CHK(apply_precond(h, h->r, h->z));
+    HIPCHK(hipMemcpyAsync(h->p, h->z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int cur = S_RZ0, nxt = S_RZ1;
+    launch_dot(s, n, h->r, h->z, h->part, h->scal + cur);
+    for (int k = 1; k <= h->opt.maxit; ++k) {
+        launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, h->p, nullptr, h->q, 0);
+        launch_dot(s, n, h->p, h->q, h->part, h->scal + S_PQ);
+        launch_cg_update_xr(s, n, h->scal, cur, S_PQ, h->p, h->q, x, h->r);
+        launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
+        CHK(read_scalars(h, S_RR, 2));
+        HIPCHK(hipGetLastError());
+        *iters = k;
+        if (!(h->h_scal[S_PQ] > 0.0))
+            return fail(XDG_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
+        rel = std::sqrt(h->h_scal[S_RR]) / nb;
+        if (k < cap) hist[k] = rel;
+        if (rel <= h->opt.rtol) return XDG_OK;
+        CHK(apply_precond(h, h->r, h->z));
+        launch_dot(s, n, h->r, h->z, h->part, h->scal + nxt);
+        launch_cg_update_p(s, n, h->scal, nxt, cur, h->z, h->p);
+        std::swap(cur, nxt);
+    }
+    return XDG_ENOCONV;
+}
+
+// Flexible GMRES(m) with classical Gram-Schmidt applied twice; Arnoldi vectors,
+// inner products and the true residual at every restart in FP64; the
+// preconditioner runs in the handle's precision.
+static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist, int cap,
+                        int* iters) {
+    Level& f = h->L[0];
+    const int64_t n = f.len();
+    const int m = h->opt.restart;
+    hipStream_t s = h->s;
+    launch_dot(s, n, b, b, h->part, h->scal + S_BB);
+    CHK(read_scalars(h, S_BB, 1));
+    const double nb = std::sqrt(h->h_scal[S_BB]);
+    *iters = 0;
+    if (nb == 0.0) {
+        HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+        if (cap > 0) hist[0] = 0.0;
+        return XDG_OK;
+    }
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    int k = 0;
+    bool first = true;
+    for (;;) {
+        // true FP64 residual (the refinement step)
+        launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0);
+        launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
+        CHK(read_scalars(h, S_RR, 1));
+        const double beta = std::sqrt(h->h_scal[S_RR]);
+        const double rel = beta / nb;
+        if (k < cap) hist[k] = rel;       // replaces the estimate of the last inner step
+        if (rel <= h->opt.rtol) return XDG_OK;
+        if (k >= h->opt.maxit) return XDG_ENOCONV;
+        if (!first && !(beta > 0.0)) return fail(XDG_EBREAKDOWN, "FGMRES: zero residual norm");
+        first = false;
+        h->h_scal[S_H] = beta;
+        HIPCHK(hipMemcpyAsync(h->scal + S_H, h->h_scal + S_H, sizeof(double),
+                              hipMemcpyHostToDevice, s));
+        launch_div_scalar(s, n, h->scal, S_H, h->r, h->V);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0, jdone = 0;
+        for (j = 0; j < m && k < h->opt.maxit; ++j) {
+            double* vj = h->V + (int64_t)j * n;
+            double* zj = h->Z + (int64_t)j * n;
+            double* vn = h->V + (int64_t)(j + 1) * n;
+            CHK(apply_precond(h, vj, zj));
+            launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, zj, nullptr, vn, 0);
+            // CGS2
+            launch_multidot(s, n, j + 1, h->V, vn, h->part, h->scal + S_H);
+            launch_multi_axpy_neg(s, n, j + 1, h->V, h->scal + S_H, vn);
+            launch_multidot(s, n, j + 1, h->V, vn, h->part, h->scal + S_H + 64);
+            launch_multi_axpy_neg(s, n, j + 1, h->V, h->scal + S_H + 64, vn);
+            launch_dot(s, n, vn, vn, h->part, h->scal + S_H + 128);
+            CHK(read_scalars(h, S_H, 129));
+            for (int i = 0; i <= j; ++i)
+                H[i * m + j] = h->h_scal[S_H + i] + h->h_scal[S_H + 64 + i];
+            const double hn = std::sqrt(h->h_scal[S_H + 128]);
+            H[(j + 1) * m + j] = hn;
+            h->h_scal[S_H + 192] = hn;
+            HIPCHK(hipMemcpyAsync(h->scal + S_H + 192, h->h_scal + S_H + 192, sizeof(double),
+                                  hipMemcpyHostToDevice, s));
+            if (hn > 0.0) launch_div_scalar(s, n, h->scal, S_H + 192, vn, vn);
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            if (!(den > 0.0)) return fail(XDG_EBREAKDOWN, "FGMRES: Arnoldi breakdown");
+            cs[j] = H[j * m + j] / den;
+            sn[j] = H[(j + 1) * m + j] / den;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++k;
+            jdone = j + 1;
+            if (k < cap) hist[k] = std::fabs(g[j + 1]) / nb;
+            *iters = k;
+            if (std::fabs(g[j + 1]) / nb <= h->opt.rtol || hn == 0.0) break;
+        }
+        // y = H^{-1} g (upper triangular), x += Z y
+        for (int i = jdone - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < jdone; ++l) t -= H[i * m + l] * y[l];
+            y[i] = t / H[i * m + i];
+        }
+        std::memcpy(h->h_scal + S_H, y.data(), jdone * sizeof(double));
+        HIPCHK(hipMemcpyAsync(h->scal + S_H, h->h_scal + S_H, jdone * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+        launch_multi_axpy(s, n, jdone, h->Z, h->scal + S_H, x);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+extern "C" int xdg_solve(xdg_handle* h, const double* b, double* x, double* hist,
+                         int32_t hist_cap, int32_t* iters, double* final_relres) {
+    if (!h || !b || !x || !iters || !final_relres || (hist_cap > 0 && !hist))
+        return fail(XDG_EINVAL, "xdg_solve: NULL argument");
+    *iters = 0;
+    int it = 0;
+    int rc = h->opt.krylov == XDG_CG ? solve_cg(h, b, x, hist, hist_cap, &it)
+                                     : solve_fgmres(h, b, x, hist, hist_cap, &it);
+    *iters = it;
+    if (rc < 0) return rc;
+    CHK(true_relres(h, b, x, final_relres));
+    if (rc == XDG_ENOCONV) g_err = "xdg_solve: iteration limit reached";
+    return rc;
+}
+
+extern "C" int xdg_get_level_matrix(xdg_handle* h, int32_t level, int32_t* row_ptr,
+                                    int32_t* col_idx, double* val) {
+    CHK(check_level(h, level, false));
+    if (!row_ptr || !col_idx || !val) return fail(XDG_EINVAL, "NULL output");
+    Level& lv = h->L[level];
+    std::copy(lv.h_rp.begin(), lv.h_rp.end(), row_ptr);
+    std::copy(lv.h_ci.begin(), lv.h_ci.end(), col_idx);
+    const int np = lv.np;
+    std::vector<double> cm((size_t)lv.nnzb * np * np);
+    HIPCHK(hipMemcpyAsync(cm.data(), lv.A64, cm.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    for (int64_t b = 0; b < lv.nnzb; ++b)
+        for (int r = 0; r < np; ++r)
+            for (int c = 0; c < np; ++c)
+                val[b * np * np + r * np + c] = cm[b * np * np + c * np + r];
+    return XDG_OK;
+}
+
+extern "C" int xdg_get_cell_inverse(xdg_handle* h, int32_t level, int32_t cell, double* out,
+                                    int32_t cap, int32_t* n) {
+    CHK(check_level(h, level, false));
+    if (!out || !n) return fail(XDG_EINVAL, "NULL output");
+    if (level == (int)h->L.size() - 1) {
+        if (cell != 0) return fail(XDG_EINVAL, "coarsest level has one block");
+        *n = h->cn;
+        if ((int64_t)h->cn * h->cn > cap) return fail(XDG_EINVAL, "output too small");
+        HIPCHK(hipMemcpy2DAsync(out, h->cn * sizeof(double), h->Cinv, h->cld * sizeof(double),
+                                h->cn * sizeof(double), h->cn, hipMemcpyDeviceToHost, h->s));
+        HIPCHK(hipStreamSynchronize(h->s));
+        return XDG_OK;
+    }
+    Level& lv = h->L[level];
+    if (cell < 0 || cell >= lv.n_cells) return fail(XDG_EINVAL, "cell out of range");
+    const int nc = (lv.h_cp[cell + 1] - lv.h_cp[cell]) * lv.np;
+    *n = nc;
+    if ((int64_t)nc * nc > cap) return fail(XDG_EINVAL, "output too small");
+    std::vector<double> cm((size_t)nc * nc);
+    HIPCHK(hipMemcpyAsync(cm.data(), lv.D64 + lv.h_doff[cell], cm.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    for (int r = 0; r < nc; ++r)
+        for (int c = 0; c < nc; ++c) out[r * nc + c] = cm[(size_t)c * nc + r];
+    return XDG_OK;
+}
+
+extern "C" int xdg_update_matrix(xdg_handle* h, const double* val_dev) {
+    if (!h || !val_dev) return fail(XDG_EINVAL, "xdg_update_matrix: NULL argument");
+    CHK(numeric_setup(h, val_dev));
+    return check_setup_error(h);
+}
+
+extern "C" int xdg_setup_time(xdg_handle* h, double* ms) {
+    if (!h || !ms) return fail(XDG_EINVAL, "NULL argument");
+    *ms = h->setup_ms;
+    return XDG_OK;
+}

@@ -1,0 +1,90 @@
+// Internal launch interface of libxdg (not part of the public C-ABI).
+//
+// Device layouts (chosen for gfx950 wave64 access):
+//   * BSR blocks are stored column-major inside each block:
+//       A[b*np*np + c*np + r] = M[m(i, r), m(col_idx[b], c)]
+//     so that for a fixed block column c the np entries of the column are
+//     contiguous; a wavefront processes floor(64/np) columns per load, one
+//     contiguous run of floor(64/np)*np elements.
+//   * cell-block inverses D_c^{-1}: dense, column-major, n_c x n_c, n_c =
+//     rows_in_cell * np, concatenated; doff[c] is the element offset.
+//   * vectors: [block row][mode].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace xdg {
+
+constexpr int kMaxCell = 88;       // largest smoother cell block order (88^2 FP64 fit 64 KB LDS)
+constexpr int kCoarseNB = 32;      // tile of the blocked coarse inversion
+
+enum SpmvMode { SPMV_AX = 0, SPMV_RESID = 1, SPMV_RESID_TRUNC = 2 };
+
+// ---- level operators (k_level.hip) -------------------------------------
+template <typename T>
+void launch_spmv(hipStream_t s, int mode, int n_rows, int np, const int* rp, const int* ci,
+                 const T* A, const T* x, const T* b, T* y, int npc);
+template <typename T>
+void launch_jacobi(hipStream_t s, bool first, int n_cells, int np, const int* cell_ptr,
+                   const int* rp, const int* ci, const T* A, const int64_t* doff, const T* D,
+                   const T* b, const T* xin, T* xout, T omega);
+template <typename T>
+void launch_restrict_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* rf, T* rc);
+template <typename T>
+void launch_prolong_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* xc, T* xf);
+template <typename T>
+void launch_restrict_dense(hipStream_t s, int n_c, int npf, int npc, const int* child_ptr,
+                           const int* child_idx, const T* R, const T* rf, T* rc);
+template <typename T>
+void launch_prolong_dense(hipStream_t s, int n_f, int npf, int npc, const int* parent,
+                          const T* R, const T* xc, T* xf);
+void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
+                        double* z);
+
+// ---- setup (k_setup.hip) -------------------------------------------------
+template <typename T>
+void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* in, T* out);
+void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const double* A,
+                            double* Ac);
+void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
+                           const int* cfb, const int* ci_row, const int* ci_col,
+                           const double* A, const double* R, double* Ac);
+void launch_gather_cells(hipStream_t s, int n_cells, int np, const int* cell_ptr,
+                         const int* rp, const int* ci, const double* A, const int64_t* doff,
+                         double* D);
+void launch_gj_batched(hipStream_t s, int n_mats, const int64_t* doff, const int* cell_ptr,
+                       int np, int max_n, double* D, int* err);
+void launch_bsr_to_dense(hipStream_t s, int n_rows, int np, const int* rp, const int* ci,
+                         const double* A, int ld, int npad, double* dense);
+void launch_coarse_gj_step(hipStream_t s, int nt, int K, int ld, double* A, double* P,
+                           int* err);
+template <typename Tin, typename Tout>
+void launch_convert(hipStream_t s, int64_t n, const Tin* in, Tout* out);
+
+// ---- vector kernels (k_blas.hip) -----------------------------------------
+constexpr int kDotBlocks = 512;
+void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial,
+                double* out);
+void launch_cg_update_xr(hipStream_t s, int64_t n, const double* scal, int i_rz, int i_pq,
+                         const double* p, const double* q, double* x, double* r);
+void launch_cg_update_p(hipStream_t s, int64_t n, const double* scal, int i_new, int i_old,
+                        const double* z, double* p);
+void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);
+void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y);
+
+}  // namespace xdg
+
+namespace xdg {
+// multi-vector kernels for FGMRES (k_blas.hip): V is [nv][n] contiguous
+void launch_multidot(hipStream_t s, int64_t n, int nv, const double* V, const double* w,
+                     double* partial, double* out);
+// w -= sum_k coef[k] V[k]   (coef in device memory)
+void launch_multi_axpy_neg(hipStream_t s, int64_t n, int nv, const double* V, const double* coef,
+                           double* w);
+// x += sum_k coef[k] V[k]
+void launch_multi_axpy(hipStream_t s, int64_t n, int nv, const double* V, const double* coef,
+                       double* x);
+// y = x / scal[i]
+void launch_div_scalar(hipStream_t s, int64_t n, const double* scal, int i, const double* x,
+                       double* y);
+}  // namespace xdg

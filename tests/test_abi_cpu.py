@@ -1,0 +1,82 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function the
+header declares, and rejects invalid input before touching the device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "xdg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(xdg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2003_02431_amd import binding
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(binding.lib(), n), n
+        assert n in binding.EXPORTED, n
+
+
+def _tiny(np_=3):
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    val = np.tile(np.eye(np_), (4, 1, 1))
+    return rp, ci, val, np.array([0, 1, 2], np.int32)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda rp, ci, v, cp: (rp, np.array([1, 0, 0, 1], np.int32), v, cp), "sorted"),
+    (lambda rp, ci, v, cp: (np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), v[:2], cp),
+     "diagonal"),
+    (lambda rp, ci, v, cp: (rp, ci, np.where(v == 1.0, np.nan, v), cp), "non-finite"),
+    (lambda rp, ci, v, cp: (rp, np.array([0, 5, 0, 1], np.int32), v, cp), "range"),
+    (lambda rp, ci, v, cp: (rp, ci, v, np.array([0, 1], np.int32)), "span"),
+])
+def test_create_rejects_invalid_input(mutate, needle):
+    from paper_2003_02431_amd import binding as B
+    rp, ci, val, cp = mutate(*_tiny())
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_create(rp, ci, val, cp, [], B.options())
+    assert e.value.code == B.XDG_EINVAL
+    assert needle in str(e.value)
+
+
+def test_create_rejects_bad_options():
+    from paper_2003_02431_amd import binding as B
+    rp, ci, val, cp = _tiny()
+    for opt in (B.options(omega=2.5), B.options(krylov=B.XDG_CG, precision=B.XDG_MIXED),
+                B.options(krylov=B.XDG_FGMRES, restart=0), B.options(nu_pre=2, nu_post=1),
+                B.options(rtol=0.0), B.options(nrhs=2)):
+        with pytest.raises(B.XdgError) as e:
+            B.xdg_create(rp, ci, val, cp, [], opt)
+        assert e.value.code == B.XDG_EINVAL
+
+
+def test_create_rejects_bad_transfer():
+    from paper_2003_02431_amd import binding as B
+    rp, ci, val, cp = _tiny()
+    bad = dict(kind=B.XDG_T_DENSE, n_rows_c=1, np_c=1, parent=np.array([0, 3], np.int32),
+               R=np.zeros((2, 3, 1)), cell_ptr_c=np.array([0, 1], np.int32))
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_create(rp, ci, val, cp, [bad], B.options())
+    assert "parent" in str(e.value)
+    trunc = dict(kind=B.XDG_T_PTRUNC, n_rows_c=2, np_c=5, parent=np.arange(2, dtype=np.int32),
+                 R=None, cell_ptr_c=np.array([0, 1, 2], np.int32))
+    with pytest.raises(B.XdgError):
+        B.xdg_create(rp, ci, val, cp, [trunc], B.options())
+
+
+def test_null_handle_calls_fail_cleanly():
+    from paper_2003_02431_amd import binding as B
+    import ctypes as C
+    assert B.lib().xdg_level_info(None, 0, None, None, None) == B.XDG_EINVAL
+    assert B.lib().xdg_vcycle(None, None, None) == B.XDG_EINVAL
+    assert "NULL" in B.xdg_last_error() or "handle" in B.xdg_last_error()
+    B.lib().xdg_destroy(None)

@@ -1,0 +1,281 @@
+"""GPU parity of every C-ABI call against the FP64 oracle on the same seeded
+problems (small sizes: full outputs; the 32^3 p=3 workload: sampled rows,
+operator identities and the oracle's own residual check).
+
+Tolerances (FP64, relative 2-norm unless stated):
+  * spmv, restriction, prolongation, Galerkin levels: 1e-13 (same products,
+    different summation order only);
+  * smoother sweeps, cell-block inverses, V-cycle, coarsest inverse: the GPU
+    inverts by Gauss-Jordan, the oracle by Cholesky; both are backward
+    stable, so they agree to ~kappa * eps -- the bound is
+    max(1e-11, 50 kappa eps) with kappa the measured condition number;
+  * solves: both reach rel.res <= 1e-10; iterates agree to the same
+    kappa-relaxed bound; iteration counts within 1.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -53
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a device"
+    return t
+
+
+def _make(name):
+    from xdg_inputs import problems
+    if name == "c1":
+        return problems.c1()
+    if name == "c2n8":
+        return problems.c2(seed=3, n=8, hier=[("p", 1), ("h", 1)])
+    if name == "c2n16":
+        return problems.c2(seed=1, n=16)
+    raise KeyError(name)
+
+
+_STATE = {}
+
+
+def _case(name, torch):
+    if name not in _STATE:
+        from oracle import mg
+        from paper_2003_02431_amd import binding as B
+        _log(f"[gpu-parity] building case {name}")
+        pr = _make(name)
+        H = mg.hierarchy_of(pr)
+        S = B.Solver(pr, B.options(rtol=1e-10, maxit=600))
+        _STATE[name] = (pr, H, S)
+    return _STATE[name]
+
+
+CASES = ["c1", "c2n8", "c2n16"]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def _kappa_tol(kappa):
+    return max(1e-11, 50.0 * kappa * EPS)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_level_matrices_and_spmv(name, torch):
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    rng = np.random.default_rng(11)
+    for l in range(H.nlev):
+        rp, ci, val = B.xdg_get_level_matrix(S.h, l)
+        G = mg.block_matrix(rp, ci, val)
+        O = H.A[l]
+        d = abs(G - O).max() / abs(O).max()
+        _log(f"  {name} level {l}: Galerkin max rel diff {d:.2e}")
+        assert d <= 1e-13
+        x = rng.uniform(-1, 1, O.shape[0])
+        y = S.vec(l)
+        B.xdg_spmv(S.h, l, S.vec(l, x), y)
+        e = _rel(y.cpu().numpy(), O @ x)
+        _log(f"  {name} level {l}: spmv rel err {e:.2e}")
+        assert e <= 1e-13
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_transfers(name, torch):
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    rng = np.random.default_rng(12)
+    for l in range(H.nlev - 1):
+        R = H.R[l]
+        rf = rng.uniform(-1, 1, R.shape[0])
+        rc = S.vec(l + 1)
+        B.xdg_restrict(S.h, l, S.vec(l, rf), rc)
+        assert _rel(rc.cpu().numpy(), R.T @ rf) <= 1e-13
+        xc = rng.uniform(-1, 1, R.shape[1])
+        xf0 = rng.uniform(-1, 1, R.shape[0])
+        xf = S.vec(l, xf0)
+        B.xdg_prolong(S.h, l, S.vec(l + 1, xc), xf)
+        assert _rel(xf.cpu().numpy(), xf0 + R @ xc) <= 1e-13
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_cell_inverses_and_smoother(name, torch):
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    rng = np.random.default_rng(13)
+    for l in range(H.nlev - 1):
+        _, invs = mg.cell_block_inverses(H.A[l], H.cell_ptr[l], H.np[l])
+        kmax = 1.0
+        for c in np.unique(np.linspace(0, len(invs) - 1, 40).astype(int)):
+            Dg = B.xdg_get_cell_inverse(S.h, l, int(c))
+            k = np.linalg.cond(invs[c])
+            kmax = max(kmax, k)
+            assert _rel(Dg, invs[c]) <= _kappa_tol(k), (l, c, k)
+        b = rng.uniform(-1, 1, H.A[l].shape[0])
+        x0 = rng.uniform(-1, 1, H.A[l].shape[0])
+        x = S.vec(l, x0)
+        B.xdg_smooth(S.h, l, S.vec(l, b), x, 2)
+        ref = mg.jacobi(H.A[l], H.Dinv[l], b, x0, 0.7, 2)
+        e = _rel(x.cpu().numpy(), ref)
+        _log(f"  {name} level {l}: smoother rel err {e:.2e} (max cell kappa {kmax:.1e})")
+        assert e <= _kappa_tol(kmax)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_coarsest_inverse(name, torch):
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    Ac = H.A[-1].toarray()
+    Cg = B.xdg_get_cell_inverse(S.h, H.nlev - 1, 0)
+    kappa = np.linalg.cond(Ac)
+    e = _rel(Cg, np.linalg.inv(Ac))
+    _log(f"  {name}: coarsest n={Ac.shape[0]} kappa={kappa:.2e} inverse rel diff {e:.2e}")
+    assert e <= _kappa_tol(kappa)
+    assert np.abs(Cg @ Ac - np.eye(Ac.shape[0])).max() <= _kappa_tol(kappa)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_vcycle(name, torch):
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    rng = np.random.default_rng(14)
+    r = rng.uniform(-1, 1, H.A[0].shape[0])
+    z = S.vec(0)
+    B.xdg_vcycle(S.h, S.vec(0, r), z)
+    ref = H.vcycle(r)
+    kappa = np.linalg.cond(H.A[-1].toarray())
+    e = _rel(z.cpu().numpy(), ref)
+    _log(f"  {name}: vcycle rel err {e:.2e} (coarse kappa {kappa:.1e})")
+    assert e <= _kappa_tol(kappa)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_pcg_solve(name, torch):
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    b = pr.b
+    xo, ho, ito = mg.pcg(H.A[0], b, H.vcycle, rtol=1e-10, maxit=600)
+    x = S.vec(0)
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0, b), x)
+    xg = x.cpu().numpy()
+    tr = np.linalg.norm(b - H.A[0] @ xg) / np.linalg.norm(b)
+    e = _rel(xg, xo)
+    hd = np.max(np.abs(hist[:min(len(hist), len(ho))] / np.array(ho[:len(hist)]) - 1.0))
+    _log(f"  {name}: PCG gpu it={it} oracle it={ito} true relres={tr:.2e} "
+         f"x rel diff={e:.2e} hist rel diff={hd:.2e}")
+    assert rc == 0 and abs(it - ito) <= 1
+    assert tr <= 1.05e-10 and abs(fr - tr) <= 1e-3 * tr
+    assert hd <= 1e-6
+    # both iterates solve to 1e-10: their distance is bounded by the error
+    # bounds, kappa(A) * 1e-10 relative; in practice rounding alone separates them
+    assert e <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["c1", "c2n16"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fgmres_solve(name, prec, torch):
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    pr, H, _ = _case(name, torch)
+    P = B.XDG_FP64 if prec == "fp64" else B.XDG_MIXED
+    rtol = 1e-10
+    S = B.Solver(pr, B.options(krylov=B.XDG_FGMRES, restart=30, precision=P, rtol=rtol,
+                               maxit=600))
+    xs, _, _ = mg.pcg(H.A[0], pr.b, H.vcycle, rtol=1e-13, maxit=1000)
+    x = S.vec(0)
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0, pr.b), x)
+    xg = x.cpu().numpy()
+    tr = np.linalg.norm(pr.b - H.A[0] @ xg) / np.linalg.norm(pr.b)
+    err = _rel(xg, xs)
+    _log(f"  {name} FGMRES {prec}: it={it} relres={tr:.2e} err vs x*={err:.2e}")
+    assert rc == 0 and tr <= 1.05 * rtol
+    assert err <= 1e-8
+    S.close()
+
+
+def test_update_matrix_and_errors(torch):
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case("c2n8", torch)
+    b = S.vec(0, pr.b)
+    x1 = S.vec(0)
+    B.xdg_solve(S.h, b, x1)
+    # same values again -> bitwise identical hierarchy and solve
+    val = torch.as_tensor(np.ascontiguousarray(pr.val)).cuda()
+    B.xdg_update_matrix(S.h, val)
+    x2 = S.vec(0)
+    B.xdg_solve(S.h, b, x2)
+    assert torch.equal(x1, x2)
+    # 2 M x = b  ->  x/2
+    B.xdg_update_matrix(S.h, 2.0 * val)
+    x3 = S.vec(0)
+    B.xdg_solve(S.h, b, x3)
+    assert _rel(x3.cpu().numpy(), 0.5 * x1.cpu().numpy()) <= 1e-9
+    B.xdg_update_matrix(S.h, val)
+    # iteration limit: status XDG_ENOCONV with a partial history
+    S2 = B.Solver(pr, B.options(maxit=2))
+    x4 = S2.vec(0)
+    rc, it, fr, hist = B.xdg_solve(S2.h, b, x4)
+    assert rc == B.XDG_ENOCONV and it == 2 and len(hist) == 3
+    S2.close()
+    # a negated diagonal block is not SPD
+    bad = pr.val.copy()
+    d0 = int(np.flatnonzero(pr.col_idx[pr.row_ptr[0]:pr.row_ptr[1]] == 0)[0])
+    bad[d0] = -bad[d0]
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_create(pr.row_ptr, pr.col_idx, bad, pr.cell_ptr, pr.transfers, B.options())
+    assert e.value.code == B.XDG_ENOTSPD
+
+
+def test_full_size_sampled(torch):
+    """The 32^3 p=3 workload in the launch configuration the benchmark uses:
+    sampled SpMV rows against the oracle, every Galerkin level in full, and
+    the oracle's residual of the GPU solution."""
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    from xdg_inputs import problems
+    _log("[gpu-parity] generating 32^3 p=3 workload")
+    pr = problems.c2(seed=0, n=32)
+    A = mg.block_matrix(pr.row_ptr, pr.col_idx, pr.val)
+    S = B.Solver(pr, B.options(rtol=1e-10, maxit=600))
+    rng = np.random.default_rng(15)
+    x = rng.uniform(-1, 1, A.shape[0])
+    y = S.vec(0)
+    B.xdg_spmv(S.h, 0, S.vec(0, x), y)
+    rows = rng.choice(pr.n_rows, 300, replace=False)
+    idx = (rows[:, None] * pr.np + np.arange(pr.np)).reshape(-1)
+    ref = A[idx] @ x
+    assert _rel(y.cpu().numpy()[idx], ref) <= 1e-13
+    _log("[gpu-parity] oracle hierarchy at 32^3")
+    H = mg.hierarchy_of(pr)
+    for l in range(1, H.nlev):
+        rp, ci, val = B.xdg_get_level_matrix(S.h, l)
+        G = mg.block_matrix(rp, ci, val)
+        assert abs(G - H.A[l]).max() / abs(H.A[l]).max() <= 1e-13
+    xs = S.vec(0)
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0, pr.b), xs)
+    tr = np.linalg.norm(pr.b - A @ xs.cpu().numpy()) / np.linalg.norm(pr.b)
+    _log(f"  32^3: PCG it={it} gpu relres={fr:.2e} oracle relres={tr:.2e}")
+    assert rc == 0 and tr <= 1.05e-10
+    # the preconditioner is symmetric: <B r1, r2> = <r1, B r2>
+    r1, r2 = rng.uniform(-1, 1, (2, A.shape[0]))
+    z1, z2 = S.vec(0), S.vec(0)
+    B.xdg_vcycle(S.h, S.vec(0, r1), z1)
+    B.xdg_vcycle(S.h, S.vec(0, r2), z2)
+    a, b = float(z1.cpu().numpy() @ r2), float(r1 @ z2.cpu().numpy())
+    assert abs(a - b) <= 1e-10 * abs(a)
+    S.close()

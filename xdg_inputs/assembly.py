@@ -27,7 +27,7 @@ import numpy as np
 from .basis import BoxBasis, PartBasis
 from .quadrature import tensor_rule
 
-C_ETA_DEFAULT = 2.0
+C_ETA_DEFAULT = 1.0
 
 
 class Penalty:

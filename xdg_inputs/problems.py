@@ -118,11 +118,11 @@ def c1(n=16, p=2):
                  hierarchy=hier, rhs="load", f=f, g_dir=lambda X, s: np.zeros(len(X)))
 
 
-def c2(seed=0, n=32, p=3, verbose=False):
+def c2(seed=0, n=32, p=3, verbose=False, hier=None):
     g = _rng.problem_rng(seed)
     ctr = _rng.sphere_jitter(g, 0.05)
     nh = int(np.log2(n)) - 3          # h-levels down to the 8^3 aggregation
-    hier = [("p", 1)] + [("h", m) for m in range(1, nh + 1)]
+    hier = hier or [("p", 1)] + [("h", m) for m in range(1, nh + 1)]
     return build(f"c2_3d_p{p}_n{n}_s{seed}", 3, n, p, Quadric.sphere(ctr, 0.6), (1.0, 1000.0),
                  hierarchy=hier, rhs="random", rng=g, verbose=verbose)
 
