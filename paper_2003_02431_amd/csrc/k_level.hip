@@ -22,13 +22,103 @@ __device__ __forceinline__ T group_sum(T acc, int np, int G) {
     return tot;
 }
 
-// (M x) restricted to block row `row`: partial sums per lane (see group_sum).
-// NP > 0 is the compile-time block size; NP == 0 uses np_rt.
+// ---------------------------------------------------------------------------
+// Row streaming.  The blocks of one block row are contiguous on the device
+// (column-major each), so the row is one stream of nb*np*np entries in which
+// entry e belongs to block column xi = e / np and matrix row e % np.  Lane l
+// owns VEC consecutive matrix rows (q = l % L, L = np/VEC lanes per column) of
+// column group cl = l / L; one load instruction of the wave covers C = 64/L
+// whole columns (C*np contiguous entries, 16-byte loads where the block size
+// allows).  The column index of block k sits in lane k's register and is
+// fetched with a cross-lane permute, so the only global loads in the loop are
+// the matrix stream and the x gather.
+
 template <typename T, int NP>
-__device__ __forceinline__ T row_times_x(int beg, int end, const int* __restrict__ ci,
-                                         const T* __restrict__ A, const T* __restrict__ x,
-                                         int lane, int np_rt) {
-    const int np = NP ? NP : np_rt;
+struct RowCfg {
+    static constexpr int VEC = sizeof(T) == 8 ? (NP % 2 == 0 ? 2 : 1)
+                                              : (NP % 4 == 0 ? 4 : (NP % 2 == 0 ? 2 : 1));
+    static constexpr int L = NP / VEC;     // lanes per column
+    static constexpr int C = 64 / L;       // columns per load instruction
+    static constexpr int CH = C * NP;      // entries per load instruction
+};
+
+template <typename T, int V> struct VecT;
+template <> struct VecT<double, 1> { using t = double; };
+template <> struct VecT<double, 2> { using t = double2; };
+template <> struct VecT<float, 1> { using t = float; };
+template <> struct VecT<float, 2> { using t = float2; };
+template <> struct VecT<float, 4> { using t = float4; };
+
+template <typename T, int V>
+__device__ __forceinline__ void load_vec(const T* p, T (&a)[V]) {
+    const typename VecT<T, V>::t v = *reinterpret_cast<const typename VecT<T, V>::t*>(p);
+    if constexpr (V == 1) {
+        a[0] = v;
+    } else if constexpr (V == 2) {
+        a[0] = v.x;
+        a[1] = v.y;
+    } else {
+        a[0] = v.x;
+        a[1] = v.y;
+        a[2] = v.z;
+        a[3] = v.w;
+    }
+}
+
+// acc[v] += sum over the row's stream; partial sums per lane (reduce with
+// reduce_groups).  b0: first block of the row, nb: number of blocks.
+template <typename T, int NP>
+__device__ __forceinline__ void row_stream(int b0, int nb, const int* __restrict__ ci,
+                                           const T* __restrict__ A, const T* __restrict__ x,
+                                           int lane, T (&acc)[RowCfg<T, NP>::VEC]) {
+    using R = RowCfg<T, NP>;
+    constexpr int V = R::VEC;
+    const int q = lane % R::L;
+    const int cl = lane / R::L;
+    const bool act = cl < R::C;
+    const int colreg = lane < nb ? ci[b0 + lane] : 0;
+    const T* Ar = A + (int64_t)b0 * (NP * NP);
+    const int E = nb * (NP * NP);
+    const int off = cl * NP + q * V;
+    for (int base = 0; base < E; base += R::CH) {
+        const int e = base + off;
+        const bool ok = act && e < E;
+        const int xi = e / NP;             // block column within the row
+        const int bb = xi / NP;            // block within the row
+        int col = __shfl(colreg, bb & 63, 64);
+        if (ok) {
+            if (bb >= 64) col = ci[b0 + bb];
+            const T xv = x[(int64_t)col * NP + (xi - bb * NP)];
+            T a[V];
+            load_vec<T, V>(Ar + e, a);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] += a[v] * xv;
+        }
+    }
+}
+
+// Sum the C column groups (lanes q, q+L, q+2L, ...) into lanes 0..L-1 with a
+// fixed-shape binary tree over the group index (log2 C shuffle rounds).
+template <typename T, int V>
+__device__ __forceinline__ void reduce_groups(T (&acc)[V], int L, int C) {
+    const int lane = threadIdx.x & 63;
+    const int cl = lane / L;
+    for (int s = 1; s < C; s <<= 1) {
+        const int src = min(lane + s * L, 63);
+        const bool take = (cl % (2 * s) == 0) && (cl + s < C);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const T o = __shfl(acc[v], src, 64);
+            if (take) acc[v] += o;
+        }
+    }
+}
+
+// Generic block size (runtime np): one column per lane group, 8-byte loads.
+template <typename T>
+__device__ __forceinline__ T row_times_x_rt(int beg, int end, const int* __restrict__ ci,
+                                            const T* __restrict__ A, const T* __restrict__ x,
+                                            int lane, int np) {
     const int G = 64 / np;
     const int r = lane % np;
     const int g = lane / np;
@@ -38,15 +128,7 @@ __device__ __forceinline__ T row_times_x(int beg, int end, const int* __restrict
             const int col = uniform(ci[blk]);
             const T* Ab = A + (int64_t)blk * (np * np) + r;
             const T* xb = x + (int64_t)col * np;
-            if constexpr (NP > 0) {
-#pragma unroll
-                for (int c0 = 0; c0 < NP; c0 += 64 / NP) {
-                    const int c = c0 + g;
-                    if (c < NP) acc += Ab[c * NP] * xb[c];
-                }
-            } else {
-                for (int c = g; c < np; c += G) acc += Ab[c * np] * xb[c];
-            }
+            for (int c = g; c < np; c += G) acc += Ab[c * np] * xb[c];
         }
     }
     return acc;
@@ -59,23 +141,65 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const i
                                                   const T* __restrict__ x,
                                                   const T* __restrict__ b, T* __restrict__ y,
                                                   int npc) {
-    const int np = NP ? NP : np_rt;
     const int lane = threadIdx.x & 63;
     const int row = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (row >= n_rows) return;
     const int beg = uniform(rp[row]), end = uniform(rp[row + 1]);
-    T acc = row_times_x<T, NP>(beg, end, ci, A, x, lane, np);
-    acc = group_sum(acc, np, 64 / np);
-    if (lane < np) {
-        const int64_t o = (int64_t)row * np + lane;
-        if (MODE == SPMV_AX) {
-            y[o] = acc;
-        } else if (MODE == SPMV_RESID) {
-            y[o] = b[o] - acc;
-        } else if (lane < npc) {
-            y[(int64_t)row * npc + lane] = b[o] - acc;
+    if constexpr (NP > 0) {
+        using R = RowCfg<T, NP>;
+        T acc[R::VEC];
+#pragma unroll
+        for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
+        row_stream<T, NP>(beg, end - beg, ci, A, x, lane, acc);
+        reduce_groups<T, R::VEC>(acc, R::L, R::C);
+        if (lane < R::L) {
+#pragma unroll
+            for (int v = 0; v < R::VEC; ++v) {
+                const int r = lane * R::VEC + v;
+                const int64_t o = (int64_t)row * NP + r;
+                if (MODE == SPMV_AX) y[o] = acc[v];
+                else if (MODE == SPMV_RESID) y[o] = b[o] - acc[v];
+                else if (r < npc) y[(int64_t)row * npc + r] = b[o] - acc[v];
+            }
+        }
+    } else {
+        const int np = np_rt;
+        T acc = row_times_x_rt<T>(beg, end, ci, A, x, lane, np);
+        acc = group_sum(acc, np, 64 / np);
+        if (lane < np) {
+            const int64_t o = (int64_t)row * np + lane;
+            if (MODE == SPMV_AX) y[o] = acc;
+            else if (MODE == SPMV_RESID) y[o] = b[o] - acc;
+            else if (lane < npc) y[(int64_t)row * npc + lane] = b[o] - acc;
         }
     }
+}
+
+// out = D r for the dense column-major n x n block D (n a multiple of V),
+// r in LDS; same column-chunk streaming as row_stream.  Lanes 0..n/V-1 end up
+// holding rows lane*V .. lane*V+V-1.
+template <typename T, int V>
+__device__ __forceinline__ void dense_apply(const T* __restrict__ D, int n, const T* r, int lane,
+                                            T (&acc)[V]) {
+    const int L = n / V;
+    const int C = 64 / L;
+    const int q = lane % L, cl = lane / L;
+    const int E = n * n, CH = C * n;
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0;
+    if (cl < C) {
+        for (int base = 0; base < E; base += CH) {
+            const int e = base + cl * n + q * V;
+            if (e < E) {
+                const T rv = r[e / n];
+                T a[V];
+                load_vec<T, V>(D + e, a);
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] += a[v] * rv;
+            }
+        }
+    }
+    reduce_groups<T, V>(acc, L, C);
 }
 
 // One damped block-Jacobi sweep for every cell block c:
@@ -100,26 +224,48 @@ __global__ __launch_bounds__(256) void k_jacobi(int n_cells, int np_rt, const in
     const int r0 = uniform(cell_ptr[cell]), r1 = uniform(cell_ptr[cell + 1]);
     const int nc = (r1 - r0) * np;
     for (int row = r0; row < r1; ++row) {
-        T acc = 0;
-        if (!FIRST) {
-            acc = row_times_x<T, NP>(uniform(rp[row]), uniform(rp[row + 1]), ci, A, xin, lane, np);
-            acc = group_sum(acc, np, 64 / np);
+        const int64_t ob = (int64_t)row * np;
+        T* rs = &res[w][(row - r0) * np];
+        if constexpr (NP > 0) {
+            using R = RowCfg<T, NP>;
+            T acc[R::VEC];
+#pragma unroll
+            for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
+            if (!FIRST) {
+                const int beg = uniform(rp[row]), end = uniform(rp[row + 1]);
+                row_stream<T, NP>(beg, end - beg, ci, A, xin, lane, acc);
+                reduce_groups<T, R::VEC>(acc, R::L, R::C);
+            }
+            if (lane < R::L) {
+#pragma unroll
+                for (int v = 0; v < R::VEC; ++v)
+                    rs[lane * R::VEC + v] = b[ob + lane * R::VEC + v] - acc[v];
+            }
+        } else {
+            T acc = 0;
+            if (!FIRST) {
+                acc = row_times_x_rt<T>(uniform(rp[row]), uniform(rp[row + 1]), ci, A, xin, lane, np);
+                acc = group_sum(acc, np, 64 / np);
+            }
+            if (lane < np) rs[lane] = b[ob + lane] - acc;
         }
-        if (lane < np) res[w][(row - r0) * np + lane] = b[(int64_t)row * np + lane] - acc;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const T* Dc = D + doff[cell];
     const int64_t base = (int64_t)r0 * np;
-    if (nc <= 64) {
-        const int G2 = 64 / nc;
-        const int o = lane % nc, g2 = lane / nc;
-        T acc = 0;
-        if (g2 < G2)
-            for (int c = g2; c < nc; c += G2) acc += Dc[(int64_t)c * nc + o] * res[w][c];
-        acc = group_sum(acc, nc, G2);
-        if (lane < nc) xout[base + lane] = (FIRST ? T(0) : xin[base + lane]) + omega * acc;
+    constexpr int V = NP > 0 ? RowCfg<T, (NP > 0 ? NP : 1)>::VEC : 1;
+    if (nc <= 64 * V) {
+        T acc[V];
+        dense_apply<T, V>(Dc, nc, res[w], lane, acc);
+        if (lane < nc / V) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int64_t o = base + lane * V + v;
+                xout[o] = (FIRST ? T(0) : xin[o]) + omega * acc[v];
+            }
+        }
     } else {
         for (int o = lane; o < nc; o += 64) {
             T acc = 0;
@@ -149,24 +295,40 @@ __global__ void k_prolong_trunc(int n_rows, int npf, int npc, const T* __restric
     xf[i * npf + a] += xc[t];
 }
 
-// rc[c][m] = sum_{i in children(c)} sum_a R_i[a][m] rf[i][a]   (children in
-// ascending order: a fixed summation order, no atomics)
+// rc[c][m] = sum_{i in children(c)} sum_a R_i[a][m] rf[i][a]: one wave per
+// coarse row; lane t takes the (child, fine mode) pairs t, t+64, ... in
+// ascending order, then a fixed butterfly sums the lanes (no atomics).
 template <typename T>
-__global__ void k_restrict_dense(int n_c, int npf, int npc, const int* __restrict__ child_ptr,
-                                 const int* __restrict__ child_idx, const T* __restrict__ R,
-                                 const T* __restrict__ rf, T* __restrict__ rc) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n_c * npc) return;
-    const int c = (int)(t / npc);
-    const int m = (int)(t - (int64_t)c * npc);
-    T acc = 0;
-    for (int k = child_ptr[c]; k < child_ptr[c + 1]; ++k) {
-        const int i = child_idx[k];
-        const T* Ri = R + (int64_t)i * npf * npc;
-        const T* ri = rf + (int64_t)i * npf;
-        for (int a = 0; a < npf; ++a) acc += Ri[a * npc + m] * ri[a];
+__global__ __launch_bounds__(256) void k_restrict_dense(int n_c, int npf, int npc,
+                                                        const int* __restrict__ child_ptr,
+                                                        const int* __restrict__ child_idx,
+                                                        const T* __restrict__ R,
+                                                        const T* __restrict__ rf,
+                                                        T* __restrict__ rc) {
+    const int lane = threadIdx.x & 63;
+    const int c = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (c >= n_c) return;
+    const int k0 = uniform(child_ptr[c]), nk = uniform(child_ptr[c + 1]) - k0;
+    T acc[kMaxTransferModes];
+#pragma unroll
+    for (int m = 0; m < kMaxTransferModes; ++m) acc[m] = 0;
+    for (int t = lane; t < nk * npf; t += 64) {
+        const int k = t / npf, a = t - k * npf;
+        const int i = child_idx[k0 + k];
+        const T rv = rf[(int64_t)i * npf + a];
+        const T* Ri = R + ((int64_t)i * npf + a) * npc;
+#pragma unroll
+        for (int m = 0; m < kMaxTransferModes; ++m)
+            if (m < npc) acc[m] += Ri[m] * rv;
     }
-    rc[t] = acc;
+#pragma unroll
+    for (int m = 0; m < kMaxTransferModes; ++m) {
+        if (m < npc) {
+            T v = acc[m];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == m) rc[(int64_t)c * npc + m] = v;
+        }
+    }
 }
 
 // xf[i][a] += sum_m R_i[a][m] xc[parent(i)][m]
@@ -185,8 +347,8 @@ __global__ void k_prolong_dense(int n_f, int npf, int npc, const int* __restrict
     xf[t] += acc;
 }
 
-// z = Ainv r, Ainv dense row-major (leading dimension ld); one wave per row,
-// fixed-order lane partials then a shuffle tree.
+// z = Ainv r, Ainv dense row-major (leading dimension ld, even); one wave per
+// row, 16-byte loads, fixed-order lane partials then a butterfly.
 __global__ __launch_bounds__(256) void k_coarse_gemv(int n, int ld, const double* __restrict__ Ainv,
                                                      const double* __restrict__ r,
                                                      double* __restrict__ z) {
@@ -195,7 +357,14 @@ __global__ __launch_bounds__(256) void k_coarse_gemv(int n, int ld, const double
     if (row >= n) return;
     const double* a = Ainv + (int64_t)row * ld;
     double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc += a[j] * r[j];
+    const int n2 = n >> 1;
+#pragma unroll 4
+    for (int j = lane; j < n2; j += 64) {
+        const double2 av = *reinterpret_cast<const double2*>(a + 2 * j);
+        const double2 rv = *reinterpret_cast<const double2*>(r + 2 * j);
+        acc += av.x * rv.x + av.y * rv.y;
+    }
+    if ((n & 1) && lane == 0) acc += a[n - 1] * r[n - 1];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) z[row] = acc;
 }
@@ -264,8 +433,7 @@ void launch_prolong_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* 
 template <typename T>
 void launch_restrict_dense(hipStream_t s, int n_c, int npf, int npc, const int* cptr,
                            const int* cidx, const T* R, const T* rf, T* rc) {
-    k_restrict_dense<T><<<nblk((int64_t)n_c * npc, 256), 256, 0, s>>>(n_c, npf, npc, cptr, cidx,
-                                                                      R, rf, rc);
+    k_restrict_dense<T><<<nblk(n_c, 4), 256, 0, s>>>(n_c, npf, npc, cptr, cidx, R, rf, rc);
 }
 template <typename T>
 void launch_prolong_dense(hipStream_t s, int n_f, int npf, int npc, const int* parent,

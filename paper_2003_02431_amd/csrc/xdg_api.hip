@@ -440,6 +440,9 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
                 return fail(XDG_EINVAL, w + ": p-truncation needs np_c <= np_f, same rows");
         } else if (tr.kind == XDG_T_DENSE) {
             if (!tr.parent || !tr.R) return fail(XDG_EINVAL, w + ": NULL parent/R");
+            if (tr.np_c > kMaxTransferModes)
+                return fail(XDG_EINVAL, w + ": dense transfer with more than " +
+                                            std::to_string(kMaxTransferModes) + " coarse modes");
             std::vector<int> cnt(tr.n_rows_c, 0);
             for (int i = 0; i < nr; ++i) {
                 if (tr.parent[i] < 0 || tr.parent[i] >= tr.n_rows_c)

@@ -17,6 +17,7 @@ namespace xdg {
 
 constexpr int kMaxCell = 88;       // largest smoother cell block order (88^2 FP64 fit 64 KB LDS)
 constexpr int kCoarseNB = 32;      // tile of the blocked coarse inversion
+constexpr int kMaxTransferModes = 8;  // coarse modes of a dense (aggregation) transfer
 
 enum SpmvMode { SPMV_AX = 0, SPMV_RESID = 1, SPMV_RESID_TRUNC = 2 };
 
