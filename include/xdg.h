@@ -21,7 +21,8 @@
  *   - every call is enqueued on the handle's HIP stream; only xdg_create,
  *     xdg_solve and the xdg_get_* copies synchronise it.
  *   - vectors are FP64, laid out [block row][mode] (row-major), length
- *     n_rows * np of the level they live on.
+ *     n_rows * np of the level they live on; a handle created with
+ *     nrhs = 16 takes 16 columns per vector, laid out [block row][mode][16].
  */
 #ifndef XDG_H
 #define XDG_H
@@ -88,7 +89,9 @@ typedef struct {
     int32_t nu_pre, nu_post;  /* block-Jacobi sweeps per level                  */
     int32_t precision;        /* XDG_FP64 | XDG_MIXED (FP32 V-cycle)            */
     int32_t smoother;         /* XDG_JACOBI                                     */
-    int32_t nrhs;             /* 1                                              */
+    int32_t nrhs;             /* 1, or 16 (needs XDG_FGMRES + XDG_MIXED): block */
+                              /* products of the V-cycle on FP32 MFMA, Arnoldi  */
+                              /* matvec and restart residuals on FP64 MFMA      */
     double  rtol;             /* stop at ||b - M x||_2 / ||b||_2 <= rtol        */
     double  omega;            /* Jacobi damping                                 */
 } xdg_options;
@@ -124,6 +127,13 @@ int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
  * residual.  Returns XDG_ENOCONV (x valid) when maxit is reached. */
 int xdg_solve(xdg_handle *h, const double *b_dev, double *x_dev, double *hist_host,
               int32_t hist_cap, int32_t *iters, double *final_relres);
+
+/* Y = M^level X for 16 columns (handle created with nrhs = 16) on the matrix
+ * cores: precision XDG_FP64 uses the FP64 blocks (level 0 only), XDG_MIXED
+ * the FP32 copy of the level (accumulation in FP32); X, Y are FP64
+ * [row][mode][16] either way. */
+int xdg_spmm(xdg_handle *h, int32_t level, int32_t precision, const double *X_dev,
+             double *Y_dev);
 
 /* Level sizes (for callers allocating level vectors). */
 int xdg_level_info(xdg_handle *h, int32_t level, int32_t *n_rows, int32_t *np,

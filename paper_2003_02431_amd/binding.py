@@ -67,6 +67,7 @@ def _load():
         "xdg_get_level_matrix": ([vp, C.c_int32, _i32p, _i32p, _f64p], C.c_int),
         "xdg_get_cell_inverse": ([vp, C.c_int32, C.c_int32, _f64p, C.c_int32, _i32p], C.c_int),
         "xdg_update_matrix": ([vp, vp], C.c_int),
+        "xdg_spmm": ([vp, C.c_int32, C.c_int32, vp, vp], C.c_int),
         "xdg_setup_time": ([vp, _f64p], C.c_int),
         "xdg_destroy": ([vp], None),
         "xdg_last_error": ([], C.c_char_p),
@@ -81,8 +82,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("xdg_create", "xdg_spmv", "xdg_smooth", "xdg_restrict", "xdg_prolong",
             "xdg_vcycle", "xdg_solve", "xdg_level_info", "xdg_get_level_matrix",
-            "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_setup_time", "xdg_destroy",
-            "xdg_last_error")
+            "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_spmm", "xdg_setup_time",
+            "xdg_destroy", "xdg_last_error")
 
 
 def lib():
@@ -197,6 +198,10 @@ def xdg_get_cell_inverse(h, level, cell, cap=1 << 24):
     return out[:n.value * n.value].reshape(n.value, n.value).copy()
 
 
+def xdg_spmm(h, level, precision, X, Y):
+    return _check(_lib.xdg_spmm(h, level, precision, _ptr(X), _ptr(Y)))
+
+
 def xdg_update_matrix(h, val_dev):
     return _check(_lib.xdg_update_matrix(h, _ptr(val_dev)))
 
@@ -231,7 +236,7 @@ class Solver:
 
     def level_len(self, level):
         n, npm, _ = xdg_level_info(self.h, level)
-        return n * npm
+        return n * npm * self.opt.nrhs
 
     def vec(self, level=0, data=None):
         t = self.torch

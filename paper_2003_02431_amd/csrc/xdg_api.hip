@@ -2,124 +2,20 @@
 // Every arithmetic step runs in the kernels of k_level.hip / k_setup.hip /
 // k_blas.hip; this file only validates input, does the integer bookkeeping of
 // the Galerkin sparsity pattern, and sequences launches on the handle's stream.
-#include <algorithm>
-#include <cmath>
-#include <cstring>
 #include <numeric>
-#include <string>
-#include <vector>
 
-#include "xdg.h"
-#include "xdg_internal.h"
+#include "xdg_handle.h"
 
 using namespace xdg;
 
-static thread_local std::string g_err;
-
-static int fail(int code, const std::string& msg) {
-    g_err = msg;
+namespace xdg {
+static thread_local std::string g_err_text;
+int fail(int code, const std::string& msg) {
+    g_err_text = msg;
     return code;
 }
-
-#define HIPCHK(x)                                                                           \
-    do {                                                                                    \
-        hipError_t e_ = (x);                                                                \
-        if (e_ != hipSuccess)                                                               \
-            return fail(e_ == hipErrorOutOfMemory ? XDG_ENOMEM : XDG_EHIP,                  \
-                        std::string(#x) + ": " + hipGetErrorString(e_));                    \
-    } while (0)
-
-#define CHK(x)                      \
-    do {                            \
-        int rc_ = (x);              \
-        if (rc_ < 0) return rc_;    \
-    } while (0)
-
-namespace {
-
-struct Level {
-    int n_rows = 0, np = 0, nnzb = 0, n_cells = 0, max_nc = 0;
-    std::vector<int> h_rp, h_ci, h_cp;
-    int *rp = nullptr, *ci = nullptr, *cp = nullptr;
-    double* A64 = nullptr;
-    float* A32 = nullptr;
-    int64_t* doff = nullptr;
-    int64_t dsize = 0;
-    std::vector<int64_t> h_doff;
-    double* D64 = nullptr;
-    float* D32 = nullptr;
-    // Galerkin contributions forming the next coarser level (dense transfers)
-    int *g_ptr = nullptr, *g_fb = nullptr, *g_row = nullptr, *g_col = nullptr;
-    // transfer to the next coarser level
-    int t_kind = -1, npc = 0, n_c = 0;
-    int *parent = nullptr, *chp = nullptr, *chi = nullptr;
-    double* R64 = nullptr;
-    float* R32 = nullptr;
-    // work vectors
-    double *b64 = nullptr, *x64 = nullptr, *y64 = nullptr, *r64 = nullptr;
-    float *b32 = nullptr, *x32 = nullptr, *y32 = nullptr, *r32 = nullptr;
-    int64_t len() const { return (int64_t)n_rows * np; }
-};
-
-template <typename T> struct P;
-template <> struct P<double> {
-    static double* A(Level& l) { return l.A64; }
-    static double* D(Level& l) { return l.D64; }
-    static double* R(Level& l) { return l.R64; }
-    static double*& b(Level& l) { return l.b64; }
-    static double*& x(Level& l) { return l.x64; }
-    static double*& y(Level& l) { return l.y64; }
-    static double*& r(Level& l) { return l.r64; }
-};
-template <> struct P<float> {
-    static float* A(Level& l) { return l.A32; }
-    static float* D(Level& l) { return l.D32; }
-    static float* R(Level& l) { return l.R32; }
-    static float*& b(Level& l) { return l.b32; }
-    static float*& x(Level& l) { return l.x32; }
-    static float*& y(Level& l) { return l.y32; }
-    static float*& r(Level& l) { return l.r32; }
-};
-
-}  // namespace
-
-struct xdg_handle {
-    hipStream_t s = nullptr;
-    xdg_options opt{};
-    std::vector<Level> L;
-    int cn = 0, cld = 0;            // coarsest order, padded leading dimension
-    double* Cinv = nullptr;
-    double* Pbuf = nullptr;         // pivot tile of the coarse inversion
-    double* scal = nullptr;         // device scalars
-    double* part = nullptr;         // reduction partials
-    double* h_scal = nullptr;       // pinned host mirror
-    int* d_err = nullptr;
-    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr;
-    double *V = nullptr, *Z = nullptr;
-    std::vector<void*> allocs;
-    double setup_ms = 0.0;
-    bool mixed = false;
-
-    template <typename T>
-    int alloc(T** ptr, size_t n) {
-        *ptr = nullptr;
-        if (n == 0) n = 1;
-        hipError_t e = hipMalloc((void**)ptr, n * sizeof(T));
-        if (e != hipSuccess) {
-            *ptr = nullptr;
-            return fail(e == hipErrorOutOfMemory ? XDG_ENOMEM : XDG_EHIP,
-                        std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        allocs.push_back((void*)*ptr);
-        return XDG_OK;
-    }
-    template <typename T>
-    int upload(T** ptr, const T* host, size_t n) {
-        CHK(alloc(ptr, n));
-        HIPCHK(hipMemcpyAsync(*ptr, host, n * sizeof(T), hipMemcpyHostToDevice, s));
-        return XDG_OK;
-    }
-};
+const std::string& last_error_text() { return g_err_text; }
+}  // namespace xdg
 
 // ---------------------------------------------------------------------------
 // validation
@@ -287,6 +183,7 @@ static int numeric_setup(xdg_handle* h, const double* raw) {
             launch_convert<double, float>(s, lv.dsize, lv.D64, lv.D32);
         }
     }
+    if (h->nrhs == kNrhs) CHK(mrhs_numeric(h));
     HIPCHK(hipGetLastError());
     return XDG_OK;
 }
@@ -396,7 +293,7 @@ static int apply_precond(xdg_handle* h, const double* r, double* z) {
 // ---------------------------------------------------------------------------
 // public API
 
-extern "C" const char* xdg_last_error(void) { return g_err.c_str(); }
+extern "C" const char* xdg_last_error(void) { return xdg::last_error_text().c_str(); }
 
 extern "C" void xdg_destroy(xdg_handle* h) {
     if (!h) return;
@@ -418,7 +315,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     if (!finite_all(A0->val, (size_t)A0->nnzb * A0->np * A0->np))
         return fail(XDG_EINVAL, "xdg_create: non-finite matrix entry");
     if (!(opt->omega > 0.0 && opt->omega < 2.0) || opt->nu_pre < 0 || opt->nu_post < 0 ||
-        opt->maxit < 1 || !(opt->rtol > 0.0) || opt->nrhs != 1 ||
+        opt->maxit < 1 || !(opt->rtol > 0.0) || (opt->nrhs != 1 && opt->nrhs != kNrhs) ||
         (opt->krylov != XDG_CG && opt->krylov != XDG_FGMRES) ||
         (opt->precision != XDG_FP64 && opt->precision != XDG_MIXED) ||
         opt->smoother != XDG_JACOBI)
@@ -429,6 +326,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
         return fail(XDG_EINVAL, "xdg_create: CG needs the FP64 (symmetric) preconditioner");
     if (opt->krylov == XDG_CG && opt->nu_pre != opt->nu_post)
         return fail(XDG_EINVAL, "xdg_create: CG needs nu_pre == nu_post (symmetric V-cycle)");
+    if (opt->nrhs == kNrhs) CHK(mrhs_validate(opt, A0->np, T, n_levels));
     int nr = A0->n_rows, npf = A0->np;
     for (int t = 0; t < n_levels - 1; ++t) {
         const xdg_transfer& tr = T[t];
@@ -466,6 +364,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
 
     h->opt = *opt;
     h->mixed = opt->precision == XDG_MIXED;
+    h->nrhs = opt->nrhs;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -536,18 +435,19 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     }
     for (auto& lv : h->L) CHK(setup_vectors(h, lv, h->mixed));
     const int64_t n0 = L0.len();
-    CHK(h->alloc(&h->scal, 256));
-    CHK(h->alloc(&h->part, (size_t)kDotBlocks * 72));
-    HIPCHK(hipHostMalloc((void**)&h->h_scal, 256 * sizeof(double), hipHostMallocDefault));
+    CHK(h->alloc(&h->scal, 4096));
+    CHK(h->alloc(&h->part, (size_t)kDotBlocks * 72 * kNrhs));
+    HIPCHK(hipHostMalloc((void**)&h->h_scal, 4096 * sizeof(double), hipHostMallocDefault));
     CHK(h->alloc(&h->r, n0));
     CHK(h->alloc(&h->z, n0));
     CHK(h->alloc(&h->p, n0));
     CHK(h->alloc(&h->q, n0));
     CHK(h->alloc(&h->w, n0));
-    if (opt->krylov == XDG_FGMRES) {
+    if (opt->krylov == XDG_FGMRES && h->nrhs == 1) {
         CHK(h->alloc(&h->V, (size_t)(opt->restart + 1) * n0));
         CHK(h->alloc(&h->Z, (size_t)opt->restart * n0));
     }
+    if (h->nrhs == kNrhs) CHK(mrhs_allocate(h));
 
     // -- numeric phase ------------------------------------------------------
     {
@@ -579,9 +479,9 @@ extern "C" int xdg_create(const xdg_matrix* A0, int32_t n_levels, const xdg_tran
     h->s = (hipStream_t)hip_stream;
     const int rc = create_impl(h, A0, n_levels, T, opt);
     if (rc < 0) {
-        const std::string msg = g_err;
+        const std::string msg = xdg::last_error_text();
         xdg_destroy(h);
-        g_err = msg;
+        fail(0, msg);
         return rc;
     }
     *out = h;
@@ -619,6 +519,7 @@ extern "C" int xdg_smooth(xdg_handle* h, int32_t level, const double* b, double*
                           int32_t sweeps) {
     CHK(check_level(h, level, true));
     if (!b || !x || sweeps < 0) return fail(XDG_EINVAL, "xdg_smooth: bad argument");
+    if (h->nrhs == kNrhs) return mrhs_smooth(h, level, b, x, sweeps);
     Level& lv = h->L[level];
     for (int k = 0; k < sweeps; ++k) {
         launch_jacobi<double>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64,
@@ -658,6 +559,7 @@ extern "C" int xdg_prolong(xdg_handle* h, int32_t level, const double* xc, doubl
 
 extern "C" int xdg_vcycle(xdg_handle* h, const double* r, double* z) {
     if (!h || !r || !z) return fail(XDG_EINVAL, "xdg_vcycle: NULL argument");
+    if (h->nrhs == kNrhs) return mrhs_vcycle(h, r, z);
     return apply_precond(h, r, z);
 }
 
@@ -828,12 +730,18 @@ extern "C" int xdg_solve(xdg_handle* h, const double* b, double* x, double* hist
         return fail(XDG_EINVAL, "xdg_solve: NULL argument");
     *iters = 0;
     int it = 0;
+    if (h->nrhs == kNrhs) {
+        const int rcm = mrhs_solve(h, b, x, hist, hist_cap, &it, final_relres);
+        *iters = it;
+        if (rcm == XDG_ENOCONV) fail(0, "xdg_solve: iteration limit reached");
+        return rcm;
+    }
     int rc = h->opt.krylov == XDG_CG ? solve_cg(h, b, x, hist, hist_cap, &it)
                                      : solve_fgmres(h, b, x, hist, hist_cap, &it);
     *iters = it;
     if (rc < 0) return rc;
     CHK(true_relres(h, b, x, final_relres));
-    if (rc == XDG_ENOCONV) g_err = "xdg_solve: iteration limit reached";
+    if (rc == XDG_ENOCONV) fail(0, "xdg_solve: iteration limit reached");
     return rc;
 }
 

@@ -1,0 +1,143 @@
+// Handle and level structures of libxdg shared by the single- and
+// multi-right-hand-side host code (not part of the public C-ABI).
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "xdg.h"
+#include "xdg_internal.h"
+
+namespace xdg {
+int fail(int code, const std::string& msg);
+const std::string& last_error_text();
+}  // namespace xdg
+using xdg::fail;
+
+#define HIPCHK(x)                                                                           \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess)                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? XDG_ENOMEM : XDG_EHIP,                  \
+                        std::string(#x) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+#define CHK(x)                      \
+    do {                            \
+        int rc_ = (x);              \
+        if (rc_ < 0) return rc_;    \
+    } while (0)
+
+namespace xdg {
+
+struct Level {
+    int n_rows = 0, np = 0, nnzb = 0, n_cells = 0, max_nc = 0;
+    std::vector<int> h_rp, h_ci, h_cp;
+    int *rp = nullptr, *ci = nullptr, *cp = nullptr;
+    double* A64 = nullptr;
+    float* A32 = nullptr;
+    int64_t* doff = nullptr;
+    int64_t dsize = 0;
+    std::vector<int64_t> h_doff;
+    double* D64 = nullptr;
+    float* D32 = nullptr;
+    // Galerkin contributions forming the next coarser level (dense transfers)
+    int *g_ptr = nullptr, *g_fb = nullptr, *g_row = nullptr, *g_col = nullptr;
+    // transfer to the next coarser level
+    int t_kind = -1, npc = 0, n_c = 0;
+    int *parent = nullptr, *chp = nullptr, *chi = nullptr;
+    double* R64 = nullptr;
+    float* R32 = nullptr;
+    // work vectors
+    double *b64 = nullptr, *x64 = nullptr, *y64 = nullptr, *r64 = nullptr;
+    float *b32 = nullptr, *x32 = nullptr, *y32 = nullptr, *r32 = nullptr;
+    // 16-column (multi-right-hand-side) data: packed FP32 blocks and inverses,
+    // packed FP64 blocks (level 0), work vectors [row][mode][16]
+    float *Ap32 = nullptr, *Dp32 = nullptr;
+    double* Ap64 = nullptr;
+    float *bm = nullptr, *xm = nullptr, *ym = nullptr, *rm = nullptr;
+    double *bm64 = nullptr, *xm64 = nullptr;
+    int64_t len() const { return (int64_t)n_rows * np; }
+};
+
+template <typename T> struct P;
+template <> struct P<double> {
+    static double* A(Level& l) { return l.A64; }
+    static double* D(Level& l) { return l.D64; }
+    static double* R(Level& l) { return l.R64; }
+    static double*& b(Level& l) { return l.b64; }
+    static double*& x(Level& l) { return l.x64; }
+    static double*& y(Level& l) { return l.y64; }
+    static double*& r(Level& l) { return l.r64; }
+};
+template <> struct P<float> {
+    static float* A(Level& l) { return l.A32; }
+    static float* D(Level& l) { return l.D32; }
+    static float* R(Level& l) { return l.R32; }
+    static float*& b(Level& l) { return l.b32; }
+    static float*& x(Level& l) { return l.x32; }
+    static float*& y(Level& l) { return l.y32; }
+    static float*& r(Level& l) { return l.r32; }
+};
+
+}  // namespace xdg
+
+using xdg::Level;
+using xdg::P;
+
+struct xdg_handle {
+    hipStream_t s = nullptr;
+    xdg_options opt{};
+    std::vector<Level> L;
+    int cn = 0, cld = 0;            // coarsest order, padded leading dimension
+    double* Cinv = nullptr;
+    double* Pbuf = nullptr;         // pivot tile of the coarse inversion
+    double* scal = nullptr;         // device scalars
+    double* part = nullptr;         // reduction partials
+    double* h_scal = nullptr;       // pinned host mirror
+    int* d_err = nullptr;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr;
+    double *V = nullptr, *Z = nullptr;
+    std::vector<void*> allocs;
+    double setup_ms = 0.0;
+    bool mixed = false;
+    int nrhs = 1;
+    // 16-column Krylov space: FP32 V, Z [k][row][mode][16], FP64 W, R
+    float *Vm = nullptr, *Zm = nullptr;
+    double *Wm = nullptr, *Rm = nullptr;
+
+    template <typename T>
+    int alloc(T** ptr, size_t n) {
+        *ptr = nullptr;
+        if (n == 0) n = 1;
+        hipError_t e = hipMalloc((void**)ptr, n * sizeof(T));
+        if (e != hipSuccess) {
+            *ptr = nullptr;
+            return fail(e == hipErrorOutOfMemory ? XDG_ENOMEM : XDG_EHIP,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        allocs.push_back((void*)*ptr);
+        return XDG_OK;
+    }
+    template <typename T>
+    int upload(T** ptr, const T* host, size_t n) {
+        CHK(alloc(ptr, n));
+        HIPCHK(hipMemcpyAsync(*ptr, host, n * sizeof(T), hipMemcpyHostToDevice, s));
+        return XDG_OK;
+    }
+};
+
+
+namespace xdg {
+// multi-right-hand-side host code (xdg_mrhs.hip)
+int mrhs_validate(const xdg_options* opt, int np0, const xdg_transfer* T, int n_levels);
+int mrhs_allocate(xdg_handle* h);
+int mrhs_numeric(xdg_handle* h);
+int mrhs_spmm(xdg_handle* h, int level, int precision, const double* X, double* Y);
+int mrhs_smooth(xdg_handle* h, int level, const double* B, double* X, int sweeps);
+int mrhs_vcycle(xdg_handle* h, const double* R, double* Z);
+int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap, int* iters,
+               double* final_relres);
+}  // namespace xdg

@@ -89,3 +89,38 @@ void launch_multi_axpy(hipStream_t s, int64_t n, int nv, const double* V, const 
 void launch_div_scalar(hipStream_t s, int64_t n, const double* scal, int i, const double* x,
                        double* y);
 }  // namespace xdg
+
+namespace xdg {
+// ---- 16-column (multi-right-hand-side) kernels (k_mrhs.hip) ---------------
+constexpr int kNrhs = 16;
+bool mrhs_np_supported(int np);
+template <typename TA, typename TX, typename TY>
+void launch_spmm(hipStream_t s, int mode, int n_rows, int np, const int* rp, const int* ci,
+                 const TA* Ap, const TX* X, const TY* B, TY* Y, int npc);
+void launch_jacobi_mrhs(hipStream_t s, bool first, int n_cells, int np, const int* cp,
+                        const int* rp, const int* ci, const float* Ap, const int64_t* doff,
+                        const float* Dp, const float* B, const float* Xin, float* Xout,
+                        float omega);
+template <typename Tout>
+void launch_pack_blocks(hipStream_t s, int64_t nblocks, int n, const double* in, Tout* out);
+void launch_pack_cells(hipStream_t s, int n_cells, int np, const int* cp, const int64_t* doff,
+                       const double* in, float* out);
+template <typename T>
+void launch_prolong_trunc_m(hipStream_t s, int n_rows, int npf, int npc, const T* xc, T* xf);
+template <typename T>
+void launch_restrict_dense_m(hipStream_t s, int n_c, int npf, int npc, const int* cptr,
+                             const int* cidx, const T* R, const T* rf, T* rc);
+template <typename T>
+void launch_prolong_dense_m(hipStream_t s, int n_f, int npf, int npc, const int* parent,
+                            const T* R, const T* xc, T* xf);
+void launch_coarse_gemm16(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
+                          double* z);
+template <typename TV>
+void launch_multidot16(hipStream_t s, int64_t n16, int nv, const TV* V, const double* w,
+                       double* partial, double* out);
+template <typename TV, typename TW>
+void launch_multi_axpy16(hipStream_t s, bool neg, int64_t n16, int nv, const TV* V,
+                         const double* coef, TW* w);
+template <typename TO>
+void launch_scale16(hipStream_t s, int64_t n16, const double* w, const double* sc, TO* out);
+}  // namespace xdg

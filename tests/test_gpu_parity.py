@@ -208,6 +208,22 @@ def test_fgmres_solve(name, prec, torch):
     S.close()
 
 
+def test_mixed_vcycle_is_fp32(torch):
+    """The mixed handle's V-cycle runs in FP32: it differs from the FP64 cycle
+    by FP32 rounding, not by zero and not by more."""
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case("c2n16", torch)
+    Sm = B.Solver(pr, B.options(krylov=B.XDG_FGMRES, precision=B.XDG_MIXED))
+    r = np.random.default_rng(16).uniform(-1, 1, H.A[0].shape[0])
+    z64, z32 = S.vec(0), Sm.vec(0)
+    B.xdg_vcycle(S.h, S.vec(0, r), z64)
+    B.xdg_vcycle(Sm.h, Sm.vec(0, r), z32)
+    d = _rel(z32.cpu().numpy(), z64.cpu().numpy())
+    _log(f"  mixed vs fp64 V-cycle rel diff {d:.2e}")
+    assert 1e-9 < d < 1e-3
+    Sm.close()
+
+
 def test_update_matrix_and_errors(torch):
     from paper_2003_02431_amd import binding as B
     pr, H, S = _case("c2n8", torch)
