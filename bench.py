@@ -116,19 +116,105 @@ class _Cached:
         return pr
 
 
-def load_problem(n, seed):
+def load_problem(n, seed, workload="c2", p=3):
     """Generate the workload (or reuse a copy saved by an earlier run of this
     benchmark in the same session when XDG_BENCH_CACHE names a directory)."""
     from xdg_inputs import problems
     cache = os.environ.get("XDG_BENCH_CACHE")
-    path = os.path.join(cache, f"c2_n{n}_s{seed}.npz") if cache else None
+    tag = f"c2_n{n}_s{seed}" if workload == "c2" else f"c4_n{n}_p{p}_s{seed}"
+    path = os.path.join(cache, tag + ".npz") if cache else None
     if path and os.path.exists(path):
         return _Cached.load(path)
-    pr = problems.c2(seed=seed, n=n)
+    if workload == "c2":
+        pr = problems.c2(seed=seed, n=n)
+    else:
+        pr = problems.c4(seed=seed, n=n, p=p, nrhs=16, verbose=True)
     if path:
         os.makedirs(cache, exist_ok=True)
         _Cached.save(pr, path)
     return pr
+
+
+def bench_multi_rhs(args):
+    """64^3 cut grid, 16 right-hand sides: MFMA block products in the FP32
+    V-cycle and the FP64 Arnoldi operator, FGMRES with FP64 restarts to 1e-8."""
+    import torch
+    from paper_2003_02431_amd import binding as B
+    torch.cuda.set_device(0)
+    log(f"[bench-c4] generating 64^3 p={args.p} workload, 16 right-hand sides")
+    t0 = time.time()
+    pr = load_problem(args.n, args.seed, "c4", args.p)
+    L = pr.n_rows * pr.np
+    log(f"[bench-c4] rows={pr.n_rows} np={pr.np} nnzb={pr.col_idx.size} in {time.time() - t0:.1f}s")
+    opt = B.options(krylov=B.XDG_FGMRES, restart=args.restart, precision=B.XDG_MIXED, nrhs=16,
+                    rtol=1e-8, maxit=2000)
+    S = B.Solver(pr, opt)
+    log(f"[bench-c4] handle created, set-up {B.xdg_setup_time(S.h):.1f} ms")
+    val_dev = torch.as_tensor(np.ascontiguousarray(pr.val)).cuda()
+    b_dev = S.vec(0, np.asarray(pr.b).reshape(L, 16))
+    x_dev = S.vec(0)
+    times, its = [], []
+    for k in range(args.warmup + args.steps):
+        x_dev.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.xdg_update_matrix(S.h, val_dev)
+        rc, it, fr, _ = B.xdg_solve(S.h, b_dev, x_dev, hist_cap=4000)
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            times.append(time.perf_counter() - t1)
+            its.append(it)
+        log(f"[bench-c4] step {k}: status {rc} iters {it} max relres {fr:.2e}")
+    # level-0 MFMA block products, 16 columns
+    st = torch.cuda.current_stream()
+    X = S.vec(0, np.random.default_rng(1).uniform(-1, 1, (L, 16)))
+    Y = S.vec(0)
+    res = {}
+    for name, prec, word, peak in (("fp32", B.XDG_MIXED, 4, 157.3), ("fp64", B.XDG_FP64, 8, 78.6)):
+        B.xdg_spmm(S.h, 0, prec, X, Y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(20):
+            B.xdg_spmm(S.h, 0, prec, X, Y)
+        e1.record(st)
+        e1.synchronize()
+        # the timed call includes the FP64<->FP32 conversions of X and Y for the FP32 product
+        t = e0.elapsed_time(e1) / 20 * 1e-3
+        nnzb = pr.col_idx.size
+        byt = nnzb * pr.np ** 2 * word + 4 * nnzb + 4 * (pr.n_rows + 1) + 2 * L * 16 * word
+        fl = 2.0 * nnzb * pr.np ** 2 * 16
+        res[name] = dict(us=round(t * 1e6, 1), gbs=round(byt / t / 1e9, 1),
+                         tflops=round(fl / t / 1e12, 2), mfma_frac=round(fl / t / 1e12 / peak, 3))
+        log(f"[bench-c4] spmm {name}: {res[name]}")
+    # one column alone through the single-right-hand-side mixed path, for the ratio
+    S1 = None
+    class _One:
+        pass
+    one = _One()
+    one.row_ptr, one.col_idx, one.val, one.cell_ptr = pr.row_ptr, pr.col_idx, pr.val, pr.cell_ptr
+    one.transfers = pr.transfers
+    S1 = B.Solver(one, B.options(krylov=B.XDG_FGMRES, restart=30, precision=B.XDG_MIXED,
+                                 rtol=1e-8, maxit=2000))
+    b1 = S1.vec(0, np.asarray(pr.b)[:, 0])
+    x1 = S1.vec(0)
+    B.xdg_solve(S1.h, b1, x1)
+    x1.zero_()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc1, it1, fr1, _ = B.xdg_solve(S1.h, b1, x1)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t1
+    S1.close()
+    out = {"metric": "16-RHS MG-FGMRES time to rel.res 1e-8 (s), 64^3 cut grid",
+           "value": round(float(np.median(times)), 4), "unit": "s", "higher_is_better": False,
+           "config": {"workload": f"xdg_sip_poisson_3d_p{args.p}_64^3_ellipsoid_mu1:1000_16rhs",
+                      "block_rows": int(pr.n_rows), "np": int(pr.np),
+                      "nnzb": int(pr.col_idx.size), "restart": args.restart},
+           "iters": its, "spmm_level0": res,
+           "single_rhs_mixed_solve_s": round(t_one, 4), "single_rhs_iters": it1,
+           "speedup_vs_16_single_solves": round(16 * t_one / float(np.median(times)), 2)}
+    print(json.dumps(out), flush=True)
+    S.close()
 
 
 def main():
@@ -140,6 +226,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+                    help="c2: 32^3 p=3 single right-hand side (default line); "
+                         "c4: 64^3 cut grid with 16 right-hand sides")
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--profile-spmv", action="store_true",
                     help="only launch the level-0 SpMV 20 times and a plain copy (counters)")
     args = ap.parse_args()
@@ -147,6 +238,12 @@ def main():
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        if args.n == 32:
+            args.n = 64
+        bench_multi_rhs(args)
+        return
 
     import torch
     from paper_2003_02431_amd import binding as B
