@@ -88,7 +88,7 @@ typedef struct {
     int32_t maxit;            /* Krylov iteration limit                         */
     int32_t nu_pre, nu_post;  /* block-Jacobi sweeps per level                  */
     int32_t precision;        /* XDG_FP64 | XDG_MIXED (FP32 V-cycle)            */
-    int32_t smoother;         /* XDG_JACOBI                                     */
+    int32_t smoother;         /* XDG_JACOBI | XDG_LEARNED (see below)           */
     int32_t nrhs;             /* 1, or 16 (needs XDG_FGMRES + XDG_MIXED): block */
                               /* products of the V-cycle on FP32 MFMA, Arnoldi  */
                               /* matvec and restart residuals on FP64 MFMA      */
@@ -158,9 +158,84 @@ int xdg_get_cell_inverse(xdg_handle *h, int32_t level, int32_t cell, double *out
  * the stream; returns XDG_ENOTSPD on a non-positive pivot. */
 int xdg_update_matrix(xdg_handle *h, const double *val_dev);
 
+/* New stopping rule for later xdg_solve calls: rtol > 0, maxit >= 1. */
+int xdg_set_tolerance(xdg_handle *h, double rtol, int32_t maxit);
+
 /* Milliseconds spent in xdg_create on the device (Galerkin products,
  * inversions), measured with HIP events. */
 int xdg_setup_time(xdg_handle *h, double *ms);
+
+/* ---- Learned per-cell smoother (a project extension, not in the paper) ----
+ * A 45 -> 64 -> 64 -> 40 multilayer perceptron (GELU after both hidden
+ * layers, FP32) corrects the first damped block-Jacobi sweep of the level-0
+ * smoother (Section 3.3) in every V-cycle.  With x_in = 0 and residual r,
+ * per smoother cell c:
+ *   j_c = omega D_c^{-1} r_c,  s_c = ||j_c||_2,
+ *   features f_c = [ j_c / s_c in species slots | cell_geom[c][0..4] ],
+ *     slots: the species-A row of the cell -> 0..19, species B -> 20..39,
+ *     zero where the cell has no row of that species;
+ *   x_c = j_c + s_c * y_c,  y_c = MLP(f_c) read back from the same slots.
+ * The map is scale-equivariant (x scales with r).  Needs np = 20 (p = 3 in
+ * 3D), nrhs = 1, XDG_FGMRES, XDG_FP64 and nu_pre >= 1; it is active once
+ * parameters (xdg_mlp_set) and cell features (xdg_set_cell_features) exist.
+ * Fallbacks: a cell whose proposal is non-finite or has ||y_c||_2 > guard
+ * keeps the plain Jacobi step (counted); an FGMRES step that reduces the
+ * residual estimate by less than a factor 0.99 while the network is active
+ * switches the network off for the rest of that solve (flexible GMRES
+ * accepts the changed preconditioner).
+ * Parameters: 9704 FP32 values, weights row-major [out][in]:
+ *   W1[64][45] b1[64] W2[64][64] b2[64] W3[40][64] b3[40]. */
+int32_t xdg_mlp_param_count(void);
+
+/* Copies the parameters from the host and resets the Adam state. */
+int xdg_mlp_set(xdg_handle *h, const float *params_host);
+
+/* Copies the current parameters to the host (synchronises). */
+int xdg_mlp_get(xdg_handle *h, float *params_host);
+
+/* Y_dev[n][40] = MLP(X_dev[n][45]). */
+int xdg_mlp_forward(xdg_handle *h, int32_t n, const float *X_dev, float *Y_dev);
+
+/* grad_dev[9704] = d loss / d parameters and *loss_host = loss for
+ * loss = sum_{s,o} (MLP(X)[s][o] - T[s][o])^2 / n (synchronises).  The sum
+ * over samples is taken in a fixed order: results are reproducible. */
+int xdg_mlp_gradient(xdg_handle *h, int32_t n, const float *X_dev, const float *T_dev,
+                     float *grad_dev, float *loss_host);
+
+/* `steps` Adam steps (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8, step
+ * size lr) on the loss above over minibatches of `batch` samples: step k uses
+ * samples [(k mod nb) * batch, +batch), nb = floor(n / batch); the caller
+ * shuffles.  loss_hist_host[k] (NULL allowed) receives the minibatch loss
+ * before step k.  The Adam step count runs on across calls until
+ * xdg_mlp_set (synchronises). */
+int xdg_mlp_train(xdg_handle *h, int32_t n, const float *X_dev, const float *T_dev,
+                  int32_t batch, int32_t steps, float lr, float *loss_hist_host);
+
+/* Level-0 cell data of the features (host arrays, copied):
+ * row_species_host[n_rows] in {0 = A (phi < 0), 1 = B}, distinct within a
+ * cell (1 or 2 rows per cell); cell_geom_host[n_cells][5] = volume fraction
+ * of species A, mean unit interface normal (zero if uncut), log10 of the
+ * diffusivity ratio mu_B / mu_A (zero if uncut). */
+int xdg_set_cell_features(xdg_handle *h, const int32_t *row_species_host,
+                          const float *cell_geom_host);
+
+/* Training pairs from an iterate x_k of a plain solve of M x = b and the
+ * converged solution xs (level-0 device vectors): with r = b - M x_k, for the
+ * cells c = cell0 + i * cell_step (i = 0 .. *n_out - 1, 0 <= cell0 < n_cells,
+ * cell_step >= 1), X_dev[i][45] = the features of r on cell c and
+ * T_dev[i][40] = (xs - x_k - j_c) / s_c in the same slots (zero where
+ * s_c = 0).  X_dev, T_dev must hold ceil((n_cells - cell0) / cell_step)
+ * samples; *n_out receives that count. */
+int xdg_learned_pairs(xdg_handle *h, const double *b_dev, const double *xk_dev,
+                      const double *xs_dev, int32_t cell0, int32_t cell_step, float *X_dev,
+                      float *T_dev, int32_t *n_out);
+
+/* Switches the smoother of an existing handle (same requirements as
+ * xdg_options.smoother) and sets the per-cell guard (> 0, default 4). */
+int xdg_set_smoother(xdg_handle *h, int32_t smoother, float guard);
+
+/* Cells that kept the plain step and solver-level fallbacks since creation. */
+int xdg_learned_stats(xdg_handle *h, int64_t *guarded_cells, int32_t *fallbacks);
 
 void xdg_destroy(xdg_handle *h);
 

@@ -21,6 +21,8 @@ XDG_FP64, XDG_MIXED = 0, 1
 XDG_JACOBI, XDG_LEARNED = 0, 1
 
 _i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_f32p = C.POINTER(C.c_float)
 _f64p = C.POINTER(C.c_double)
 
 
@@ -69,6 +71,18 @@ def _load():
         "xdg_update_matrix": ([vp, vp], C.c_int),
         "xdg_spmm": ([vp, C.c_int32, C.c_int32, vp, vp], C.c_int),
         "xdg_setup_time": ([vp, _f64p], C.c_int),
+        "xdg_mlp_param_count": ([], C.c_int32),
+        "xdg_mlp_set": ([vp, _f32p], C.c_int),
+        "xdg_mlp_get": ([vp, _f32p], C.c_int),
+        "xdg_mlp_forward": ([vp, C.c_int32, vp, vp], C.c_int),
+        "xdg_mlp_gradient": ([vp, C.c_int32, vp, vp, vp, _f32p], C.c_int),
+        "xdg_mlp_train": ([vp, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_float, _f32p],
+                          C.c_int),
+        "xdg_set_cell_features": ([vp, _i32p, _f32p], C.c_int),
+        "xdg_learned_pairs": ([vp, vp, vp, vp, C.c_int32, C.c_int32, vp, vp, _i32p], C.c_int),
+        "xdg_set_tolerance": ([vp, C.c_double, C.c_int32], C.c_int),
+        "xdg_set_smoother": ([vp, C.c_int32, C.c_float], C.c_int),
+        "xdg_learned_stats": ([vp, _i64p, _i32p], C.c_int),
         "xdg_destroy": ([vp], None),
         "xdg_last_error": ([], C.c_char_p),
     }
@@ -83,7 +97,10 @@ _lib = _load()
 EXPORTED = ("xdg_create", "xdg_spmv", "xdg_smooth", "xdg_restrict", "xdg_prolong",
             "xdg_vcycle", "xdg_solve", "xdg_level_info", "xdg_get_level_matrix",
             "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_spmm", "xdg_setup_time",
-            "xdg_destroy", "xdg_last_error")
+            "xdg_mlp_param_count", "xdg_mlp_set", "xdg_mlp_get", "xdg_mlp_forward",
+            "xdg_mlp_gradient", "xdg_mlp_train", "xdg_set_cell_features", "xdg_learned_pairs",
+            "xdg_set_smoother", "xdg_learned_stats", "xdg_set_tolerance", "xdg_destroy",
+            "xdg_last_error")
 
 
 def lib():
@@ -102,6 +119,15 @@ def _ptr(t):
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
             and t.is_contiguous()):
         raise TypeError("expected a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _ptr32(t):
+    """Device pointer of a contiguous float32 torch tensor."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 device tensor")
     return C.c_void_p(t.data_ptr())
 
 
@@ -212,6 +238,72 @@ def xdg_setup_time(h):
     return ms.value
 
 
+def xdg_mlp_param_count():
+    return int(_lib.xdg_mlp_param_count())
+
+
+def xdg_mlp_set(h, params):
+    p = _np(params, np.float32)
+    if p.size != xdg_mlp_param_count():
+        raise ValueError("wrong parameter count")
+    return _check(_lib.xdg_mlp_set(h, p.ctypes.data_as(_f32p)))
+
+
+def xdg_mlp_get(h):
+    p = np.zeros(xdg_mlp_param_count(), np.float32)
+    _check(_lib.xdg_mlp_get(h, p.ctypes.data_as(_f32p)))
+    return p
+
+
+def xdg_mlp_forward(h, X, Y):
+    return _check(_lib.xdg_mlp_forward(h, X.shape[0], _ptr32(X), _ptr32(Y)))
+
+
+def xdg_mlp_gradient(h, X, T, grad):
+    """Fills grad (float32 device tensor) and returns the loss."""
+    loss = C.c_float()
+    _check(_lib.xdg_mlp_gradient(h, X.shape[0], _ptr32(X), _ptr32(T), _ptr32(grad),
+                                 C.byref(loss)))
+    return loss.value
+
+
+def xdg_mlp_train(h, X, T, batch, steps, lr):
+    """Returns the minibatch loss history (numpy float32, one per step)."""
+    hist = np.zeros(max(steps, 1), np.float32)
+    _check(_lib.xdg_mlp_train(h, X.shape[0], _ptr32(X), _ptr32(T), batch, steps, lr,
+                              hist.ctypes.data_as(_f32p)))
+    return hist[:steps]
+
+
+def xdg_set_cell_features(h, row_species, cell_geom):
+    rs = _np(row_species, np.int32)
+    g = _np(cell_geom, np.float32)
+    return _check(_lib.xdg_set_cell_features(h, rs.ctypes.data_as(_i32p),
+                                             g.ctypes.data_as(_f32p)))
+
+
+def xdg_learned_pairs(h, b, xk, xs, cell0, cell_step, X, T):
+    """Writes the pairs into X, T (float32 device tensors); returns the count."""
+    n = C.c_int32()
+    _check(_lib.xdg_learned_pairs(h, _ptr(b), _ptr(xk), _ptr(xs), cell0, cell_step, _ptr32(X),
+                                  _ptr32(T), C.byref(n)))
+    return n.value
+
+
+def xdg_set_tolerance(h, rtol, maxit):
+    return _check(_lib.xdg_set_tolerance(h, rtol, maxit))
+
+
+def xdg_set_smoother(h, smoother, guard=4.0):
+    return _check(_lib.xdg_set_smoother(h, smoother, guard))
+
+
+def xdg_learned_stats(h):
+    g, f = C.c_int64(), C.c_int32()
+    _check(_lib.xdg_learned_stats(h, C.byref(g), C.byref(f)))
+    return g.value, f.value
+
+
 def xdg_destroy(h):
     _lib.xdg_destroy(h)
 
@@ -233,6 +325,13 @@ class Solver:
         self.h = xdg_create(problem.row_ptr, problem.col_idx, problem.val, problem.cell_ptr,
                             problem.transfers, self.opt, stream)
         self.nlev = len(problem.transfers) + 1
+        self.n_cells = len(problem.cell_ptr) - 1
+        self.smoother, self.guard = self.opt.smoother, 4.0
+
+    def set_smoother(self, smoother, guard=None):
+        self.guard = self.guard if guard is None else guard
+        xdg_set_smoother(self.h, smoother, self.guard)
+        self.smoother = smoother
 
     def level_len(self, level):
         n, npm, _ = xdg_level_info(self.h, level)

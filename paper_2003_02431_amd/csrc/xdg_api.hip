@@ -254,7 +254,14 @@ static void vcycle(xdg_handle* h, int l) {
         return;
     }
     Level& c = h->L[l + 1];
-    smooth_from_zero<T>(h, f, h->opt.nu_pre);
+    bool learned = false;
+    if constexpr (std::is_same<T, double>::value) learned = l == 0 && xdg::learned_active(h);
+    if (learned) {
+        xdg::learned_first_sweep(h, f);
+        smooth_more<T>(h, f, h->opt.nu_pre - 1);
+    } else {
+        smooth_from_zero<T>(h, f, h->opt.nu_pre);
+    }
     if (f.t_kind == XDG_T_PTRUNC) {
         launch_spmv<T>(h->s, SPMV_RESID_TRUNC, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f),
                        P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np);
@@ -317,9 +324,9 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     if (!(opt->omega > 0.0 && opt->omega < 2.0) || opt->nu_pre < 0 || opt->nu_post < 0 ||
         opt->maxit < 1 || !(opt->rtol > 0.0) || (opt->nrhs != 1 && opt->nrhs != kNrhs) ||
         (opt->krylov != XDG_CG && opt->krylov != XDG_FGMRES) ||
-        (opt->precision != XDG_FP64 && opt->precision != XDG_MIXED) ||
-        opt->smoother != XDG_JACOBI)
+        (opt->precision != XDG_FP64 && opt->precision != XDG_MIXED))
         return fail(XDG_EINVAL, "xdg_create: invalid options");
+    CHK(xdg::learned_validate(opt, A0->np));
     if (opt->krylov == XDG_FGMRES && (opt->restart < 1 || opt->restart > 64))
         return fail(XDG_EINVAL, "xdg_create: FGMRES restart must be in [1, 64]");
     if (opt->krylov == XDG_CG && opt->precision != XDG_FP64)
@@ -648,6 +655,7 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
         return XDG_OK;
     }
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    h->learned_off = false;
     int k = 0;
     bool first = true;
     for (;;) {
@@ -702,8 +710,15 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
             sn[j] = H[(j + 1) * m + j] / den;
             H[j * m + j] = den;
             H[(j + 1) * m + j] = 0.0;
+            const double gprev = std::fabs(g[j]);
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
+            // residual-decrease test of the learned smoother: a step that
+            // leaves the residual estimate almost unchanged switches it off
+            if (xdg::learned_active(h) && std::fabs(g[j + 1]) > xdg::kLearnedStall * gprev) {
+                h->learned_off = true;
+                h->learned_fallbacks += 1;
+            }
             ++k;
             jdone = j + 1;
             if (k < cap) hist[k] = std::fabs(g[j + 1]) / nb;
@@ -795,6 +810,14 @@ extern "C" int xdg_update_matrix(xdg_handle* h, const double* val_dev) {
     if (!h || !val_dev) return fail(XDG_EINVAL, "xdg_update_matrix: NULL argument");
     CHK(numeric_setup(h, val_dev));
     return check_setup_error(h);
+}
+
+extern "C" int xdg_set_tolerance(xdg_handle* h, double rtol, int32_t maxit) {
+    if (!h) return fail(XDG_EINVAL, "xdg_set_tolerance: NULL handle");
+    if (!(rtol > 0.0) || maxit < 1) return fail(XDG_EINVAL, "xdg_set_tolerance: bad rtol or maxit");
+    h->opt.rtol = rtol;
+    h->opt.maxit = maxit;
+    return XDG_OK;
 }
 
 extern "C" int xdg_setup_time(xdg_handle* h, double* ms) {

@@ -107,6 +107,19 @@ struct xdg_handle {
     // 16-column Krylov space: FP32 V, Z [k][row][mode][16], FP64 W, R
     float *Vm = nullptr, *Zm = nullptr;
     double *Wm = nullptr, *Rm = nullptr;
+    // learned smoother: network parameters, Adam moments, gradient buffers,
+    // per-row species and per-cell geometry features of level 0
+    float *mlp_w = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr;
+    float *mlp_part = nullptr, *mlp_ploss = nullptr, *mlp_loss = nullptr;
+    int mlp_blocks = 256;           // one 4-wave block per CU (register-bound)
+    int64_t mlp_step = 0;
+    int* row_species = nullptr;
+    float* cell_geom = nullptr;
+    int* d_nguard = nullptr;
+    float guard = 4.0f;             // |proposal| / |Jacobi step| above this: plain step
+    bool learned_ready = false;     // weights and features present
+    bool learned_off = false;       // solver-level fallback taken in this solve
+    int learned_fallbacks = 0;      // solver-level fallbacks (all solves)
 
     template <typename T>
     int alloc(T** ptr, size_t n) {
@@ -140,4 +153,12 @@ int mrhs_smooth(xdg_handle* h, int level, const double* B, double* X, int sweeps
 int mrhs_vcycle(xdg_handle* h, const double* R, double* Z);
 int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap, int* iters,
                double* final_relres);
+}  // namespace xdg
+
+namespace xdg {
+// learned smoother host code (xdg_mlp.hip)
+constexpr double kLearnedStall = 0.99;    // FGMRES reduction factor that disables the network
+int learned_validate(const xdg_options* opt, int np0);
+bool learned_active(xdg_handle* h);
+void learned_first_sweep(xdg_handle* h, Level& lv);
 }  // namespace xdg

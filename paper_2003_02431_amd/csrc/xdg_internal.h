@@ -124,3 +124,22 @@ void launch_multi_axpy16(hipStream_t s, bool neg, int64_t n16, int nv, const TV*
 template <typename TO>
 void launch_scale16(hipStream_t s, int64_t n16, const double* w, const double* sc, TO* out);
 }  // namespace xdg
+
+namespace xdg {
+// ---- learned smoother network (k_mlp.hip) ---------------------------------
+int mlp_param_count();
+void launch_mlp_forward(hipStream_t s, int n, const float* params, const float* X, float* Y);
+void launch_mlp_grad(hipStream_t s, int n, int n_total, int n_blocks, const float* params,
+                     const float* X, const float* T, float* partial, float* partial_loss,
+                     float* grad, float* loss);
+void launch_adam(hipStream_t s, float* w, const float* g, float* m, float* v, float lr, float b1,
+                 float b2, float c1, float c2, float eps);
+void launch_learned_first(hipStream_t s, int n_cells, const int* cp, const int* row_species,
+                          const float* geom, const int64_t* doff, const double* D,
+                          const double* b, const float* params, double omega, float guard,
+                          double* x, int* nguard);
+void launch_learned_features(hipStream_t s, int n_sel, int cell0, int cell_step, const int* cp,
+                             const int* row_species, const float* geom, const int64_t* doff,
+                             const double* D, const double* r, const double* xk,
+                             const double* xs, double omega, float* Xf, float* Tf);
+}  // namespace xdg

@@ -80,3 +80,31 @@ def test_null_handle_calls_fail_cleanly():
     assert B.lib().xdg_vcycle(None, None, None) == B.XDG_EINVAL
     assert "NULL" in B.xdg_last_error() or "handle" in B.xdg_last_error()
     B.lib().xdg_destroy(None)
+
+
+def test_learned_smoother_requirements_and_null_calls():
+    from paper_2003_02431_amd import binding as B
+    rp, ci, val, cp = _tiny()
+    # np = 3: the learned smoother needs np = 20, FGMRES, FP64, one column
+    for opt in (B.options(krylov=B.XDG_FGMRES, smoother=B.XDG_LEARNED),
+                B.options(krylov=B.XDG_CG, smoother=B.XDG_LEARNED),
+                B.options(krylov=B.XDG_FGMRES, smoother=7)):
+        with pytest.raises(B.XdgError) as e:
+            B.xdg_create(rp, ci, val, cp, [], opt)
+        assert e.value.code == B.XDG_EINVAL
+    rp, ci, val, cp = _tiny(20)
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_create(rp, ci, val, cp, [], B.options(krylov=B.XDG_FGMRES, nu_pre=0, nu_post=0,
+                                                    smoother=B.XDG_LEARNED))
+    assert "nu_pre" in str(e.value)
+    lib = B.lib()
+    assert B.xdg_mlp_param_count() == 45 * 64 + 64 + 64 * 64 + 64 + 40 * 64 + 40
+    for rc in (lib.xdg_mlp_set(None, None), lib.xdg_mlp_get(None, None),
+               lib.xdg_mlp_forward(None, 1, None, None),
+               lib.xdg_mlp_gradient(None, 1, None, None, None, None),
+               lib.xdg_mlp_train(None, 1, None, None, 1, 1, 1e-3, None),
+               lib.xdg_set_cell_features(None, None, None),
+               lib.xdg_learned_pairs(None, None, None, None, 0, 1, None, None, None),
+               lib.xdg_set_tolerance(None, 1e-8, 10),
+               lib.xdg_set_smoother(None, 0, 4.0), lib.xdg_learned_stats(None, None, None)):
+        assert rc == B.XDG_EINVAL
