@@ -87,10 +87,11 @@ def cpu_baseline(pr, gpu_iters, budget_iters=8):
 class _Cached:
     """The solver inputs of a generated problem (what the boundary takes in)."""
     KEYS = ("row_ptr", "col_idx", "val", "cell_ptr", "b")
+    OPTIONAL = ("row_species", "cell_geom")
 
     @staticmethod
     def save(pr, path):
-        d = {k: getattr(pr, k) for k in _Cached.KEYS}
+        d = {k: getattr(pr, k) for k in _Cached.KEYS + _Cached.OPTIONAL if hasattr(pr, k)}
         d["meta"] = np.array([pr.n_rows, pr.np, len(pr.transfers)])
         for t, T in enumerate(pr.transfers):
             d[f"t{t}_meta"] = np.array([T["kind"], T["n_rows_c"], T["np_c"]])
@@ -106,6 +107,9 @@ class _Cached:
         pr = _Cached()
         for k in _Cached.KEYS:
             setattr(pr, k, z[k])
+        for k in _Cached.OPTIONAL:
+            if k in z:
+                setattr(pr, k, z[k])
         pr.n_rows, pr.np, nt = (int(v) for v in z["meta"])
         pr.transfers = []
         for t in range(nt):
@@ -118,17 +122,25 @@ class _Cached:
 
 def load_problem(n, seed, workload="c2", p=3):
     """Generate the workload (or reuse a copy saved by an earlier run of this
-    benchmark in the same session when XDG_BENCH_CACHE names a directory)."""
+    benchmark in the same session when XDG_BENCH_CACHE names a directory).
+    c5: the 64^3 ellipsoid family with one right-hand side plus the learned
+    smoother's cell features."""
     from xdg_inputs import problems
     cache = os.environ.get("XDG_BENCH_CACHE")
-    tag = f"c2_n{n}_s{seed}" if workload == "c2" else f"c4_n{n}_p{p}_s{seed}"
+    tag = {"c2": f"c2_n{n}_s{seed}", "c4": f"c4_n{n}_p{p}_s{seed}",
+           "c5": f"c5_n{n}_p{p}_s{seed}"}[workload]
     path = os.path.join(cache, tag + ".npz") if cache else None
     if path and os.path.exists(path):
         return _Cached.load(path)
     if workload == "c2":
         pr = problems.c2(seed=seed, n=n)
-    else:
+    elif workload == "c4":
         pr = problems.c4(seed=seed, n=n, p=p, nrhs=16, verbose=True)
+    else:
+        from xdg_inputs import features
+        pr = problems.c4(seed=seed, n=n, p=p, nrhs=1, verbose=True)
+        pr.b = np.asarray(pr.b).reshape(-1)
+        pr.row_species, pr.cell_geom = features.cell_features(pr)
     if path:
         os.makedirs(cache, exist_ok=True)
         _Cached.save(pr, path)
@@ -217,6 +229,102 @@ def bench_multi_rhs(args):
     S.close()
 
 
+def bench_learned(args):
+    """64^3 p=3 random-ellipsoid interface, one right-hand side: the learned
+    per-cell smoother trained on the GPU from 2e5 residual/error pairs of
+    plain solves on another interface, then FGMRES(30) with and without it,
+    each to a solution error <= 1e-8 against the tightly converged FP64
+    solution."""
+    import torch
+    from paper_2003_02431_amd import binding as B, learned as LS
+    torch.cuda.set_device(0)
+    clip, guard = 0.25, 0.5
+    opt = dict(krylov=B.XDG_FGMRES, restart=30, rtol=1e-10, maxit=2000)
+
+    def solver(pr, sm):
+        S = B.Solver(pr, B.options(smoother=sm, **opt))
+        B.xdg_set_cell_features(S.h, pr.row_species, pr.cell_geom)
+        return S
+
+    def tight(S, b):
+        x = S.vec(0)
+        B.xdg_set_tolerance(S.h, 1e-13, 4000)
+        B.xdg_solve(S.h, b, x, hist_cap=5000)
+        B.xdg_set_tolerance(S.h, opt["rtol"], opt["maxit"])
+        return x
+
+    t0 = time.time()
+    tr = load_problem(args.n, args.seed + 1, "c5", 3)
+    log(f"[bench-c5] training interface: rows={tr.n_rows} cells={len(tr.cell_ptr) - 1} "
+        f"({time.time() - t0:.1f}s)")
+    St = solver(tr, B.XDG_JACOBI)
+    bt = St.vec(0, tr.b)
+    xst = tight(St, bt)
+    n_cells = St.n_cells
+    step = max(1, int(round(8 * n_cells / 2e5)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X, T = LS.plain_pairs(St, bt, xst, iterates=range(8), cell_step=step, clip=clip)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t1
+    St.close()
+    log(f"[bench-c5] {X.shape[0]} pairs (cell step {step}) in {t_pairs:.2f}s")
+
+    t0 = time.time()
+    pr = load_problem(args.n, args.seed, "c5", 3)
+    log(f"[bench-c5] test interface: rows={pr.n_rows} nnzb={pr.col_idx.size} "
+        f"({time.time() - t0:.1f}s)")
+    S = solver(pr, B.XDG_LEARNED)
+    B.xdg_set_smoother(S.h, B.XDG_LEARNED, guard)
+    S.guard = guard
+    B.xdg_mlp_set(S.h, LS.init_params(0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = LS.train(S, X, T, steps=600, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    log(f"[bench-c5] trained 600 full-batch Adam steps in {t_train:.2f}s, loss {hist[0]:.4f} -> "
+        f"{hist[-1]:.4f}")
+    b = S.vec(0, pr.b)
+    xs = tight(S, b)
+    res = {}
+    for name, sm in (("plain", B.XDG_JACOBI), ("learned", B.XDG_LEARNED)):
+        S.set_smoother(sm)
+        x = S.vec(0)
+        B.xdg_solve(S.h, b, x, hist_cap=3000)     # warm-up
+        ts = []
+        for _ in range(max(1, args.steps)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rc, it, fr, _ = B.xdg_solve(S.h, b, x, hist_cap=3000)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
+        res[name] = dict(time_s=round(float(np.median(ts)), 5), iters=it, relres=fr, err=err,
+                         status=rc)
+        log(f"[bench-c5] {name}: {res[name]}")
+    gd, fb = B.xdg_learned_stats(S.h)
+    S.close()
+    out = {"metric": "MG-FGMRES time to solution error 1e-8 (s), learned vs plain smoother, "
+                     "64^3 p=3 cut grid",
+           "value": res["learned"]["time_s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f64+f32",
+           "data": "synthetic",
+           "config": {"workload": "xdg_sip_poisson_3d_p3_64^3_random_ellipsoid_mu1:1000_learned",
+                      "block_rows": int(pr.n_rows), "nnzb": int(pr.col_idx.size),
+                      "train_pairs": int(X.shape[0]), "clip": clip, "guard": guard,
+                      "krylov": "FGMRES(30)", "rtol": opt["rtol"]},
+           "plain": res["plain"], "learned": res["learned"],
+           "iteration_gain": res["plain"]["iters"] - res["learned"]["iters"],
+           "time_ratio_learned_over_plain": round(res["learned"]["time_s"] /
+                                                  res["plain"]["time_s"], 3),
+           "pairs_s": round(t_pairs, 3), "train_s": round(t_train, 3),
+           "train_loss": [float(hist[0]), float(hist[-1])],
+           "guarded_cells": gd, "solver_fallbacks": fb}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,9 +334,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
                     help="c2: 32^3 p=3 single right-hand side (default line); "
-                         "c4: 64^3 cut grid with 16 right-hand sides")
+                         "c4: 64^3 cut grid with 16 right-hand sides; "
+                         "c5: 64^3 p=3 with the learned smoother")
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--profile-spmv", action="store_true",
@@ -239,10 +348,10 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "c4":
+    if args.workload in ("c4", "c5"):
         if args.n == 32:
             args.n = 64
-        bench_multi_rhs(args)
+        (bench_multi_rhs if args.workload == "c4" else bench_learned)(args)
         return
 
     import torch
@@ -329,11 +438,26 @@ def main():
             torch.cuda.synchronize()
             tm.append(time.perf_counter() - t2)
         errm = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
+        # the same form run until its solution error is <= 1e-8 (rel.res 1e-9)
+        B.xdg_set_tolerance(Sm.h, 1e-9, 1000)
+        te = []
+        for _ in range(3):
+            xm.zero_()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            B.xdg_update_matrix(Sm.h, val_dev)
+            rce, ite, fre, _ = B.xdg_solve(Sm.h, b_dev, xm, hist_cap=2000)
+            torch.cuda.synchronize()
+            te.append(time.perf_counter() - t2)
+        erre = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
         mixed = dict(time_s=round(float(np.median(tm)), 5), iters=itm, relres=frm,
                      err_vs_fp64=errm, krylov="FGMRES(30)",
+                     at_err_1e_8=dict(rtol=1e-9, time_s=round(float(np.median(te)), 5),
+                                      iters=ite, relres=fre, err_vs_fp64=erre),
                      note="FP32 V-cycle (A, D^-1, R in FP32), FP64 Arnoldi, SpMV in "
                           "Arnoldi, residuals and coarsest inverse")
-        log(f"[bench] mixed: {tm} iters {itm} relres {frm:.2e} err {errm:.2e}")
+        log(f"[bench] mixed: {tm} iters {itm} relres {frm:.2e} err {errm:.2e}; "
+            f"to err<=1e-8: {te} iters {ite} err {erre:.2e}")
         Sm.close()
 
     # roofline of the level-0 block SpMV

@@ -224,11 +224,12 @@ int xdg_set_cell_features(xdg_handle *h, const int32_t *row_species_host,
  * cells c = cell0 + i * cell_step (i = 0 .. *n_out - 1, 0 <= cell0 < n_cells,
  * cell_step >= 1), X_dev[i][45] = the features of r on cell c and
  * T_dev[i][40] = (xs - x_k - j_c) / s_c in the same slots (zero where
- * s_c = 0).  X_dev, T_dev must hold ceil((n_cells - cell0) / cell_step)
- * samples; *n_out receives that count. */
+ * s_c = 0), scaled to norm `clip` where it is longer (clip = 0: no scaling).
+ * X_dev, T_dev must hold ceil((n_cells - cell0) / cell_step) samples;
+ * *n_out receives that count. */
 int xdg_learned_pairs(xdg_handle *h, const double *b_dev, const double *xk_dev,
-                      const double *xs_dev, int32_t cell0, int32_t cell_step, float *X_dev,
-                      float *T_dev, int32_t *n_out);
+                      const double *xs_dev, int32_t cell0, int32_t cell_step, float clip,
+                      float *X_dev, float *T_dev, int32_t *n_out);
 
 /* Switches the smoother of an existing handle (same requirements as
  * xdg_options.smoother) and sets the per-cell guard (> 0, default 4). */

@@ -15,7 +15,9 @@ V-cycle.  With x_in = 0 and residual r, per smoother cell c (rows
 unless y_c is non-finite or ||y_c||_2 > guard, then x_c = j_c.
 Training pairs from an iterate x_k of a plain solve (residual r_k = b - M x_k)
 and the converged x*: features of r_k, target (x* - x_k - j_c) / s_c in the
-same slots.
+same slots, optionally scaled down to a maximum norm (the error of a smooth
+mode is many Jacobi steps long and no cell-local map can predict it; the
+clipped target keeps the network's proposal in the range of a sweep).
 """
 import numpy as np
 
@@ -65,8 +67,9 @@ def first_sweep(H, row_species, cell_geom, theta, r, guard):
     return x.reshape(-1), int(bad.sum())
 
 
-def pairs(H, row_species, cell_geom, b, xk, xs):
-    """(X [n_cells, 45], T [n_cells, 40]) training pairs of iterate xk."""
+def pairs(H, row_species, cell_geom, b, xk, xs, clip=0.0):
+    """(X [n_cells, 45], T [n_cells, 40]) training pairs of iterate xk; with
+    clip > 0 every target longer than clip is scaled to length clip."""
     r = b - H.A[0] @ xk
     F, j, s = features(H, row_species, cell_geom, r)
     cp = H.cell_ptr[0]
@@ -77,6 +80,10 @@ def pairs(H, row_species, cell_geom, b, xk, xs):
     for row in range(E.shape[0]):
         c = cell_of_row[row]
         T[c, slot0[row]:slot0[row] + NP] = E[row] * inv[c]
+    if clip > 0.0:
+        nt = np.linalg.norm(T, axis=1)
+        big = nt > clip
+        T[big] *= (clip / nt[big])[:, None]
     return F, T
 
 

@@ -79,7 +79,8 @@ def _load():
         "xdg_mlp_train": ([vp, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_float, _f32p],
                           C.c_int),
         "xdg_set_cell_features": ([vp, _i32p, _f32p], C.c_int),
-        "xdg_learned_pairs": ([vp, vp, vp, vp, C.c_int32, C.c_int32, vp, vp, _i32p], C.c_int),
+        "xdg_learned_pairs": ([vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, vp, vp, _i32p],
+                              C.c_int),
         "xdg_set_tolerance": ([vp, C.c_double, C.c_int32], C.c_int),
         "xdg_set_smoother": ([vp, C.c_int32, C.c_float], C.c_int),
         "xdg_learned_stats": ([vp, _i64p, _i32p], C.c_int),
@@ -282,11 +283,11 @@ def xdg_set_cell_features(h, row_species, cell_geom):
                                              g.ctypes.data_as(_f32p)))
 
 
-def xdg_learned_pairs(h, b, xk, xs, cell0, cell_step, X, T):
+def xdg_learned_pairs(h, b, xk, xs, cell0, cell_step, X, T, clip=0.0):
     """Writes the pairs into X, T (float32 device tensors); returns the count."""
     n = C.c_int32()
-    _check(_lib.xdg_learned_pairs(h, _ptr(b), _ptr(xk), _ptr(xs), cell0, cell_step, _ptr32(X),
-                                  _ptr32(T), C.byref(n)))
+    _check(_lib.xdg_learned_pairs(h, _ptr(b), _ptr(xk), _ptr(xs), cell0, cell_step, clip,
+                                  _ptr32(X), _ptr32(T), C.byref(n)))
     return n.value
 
 

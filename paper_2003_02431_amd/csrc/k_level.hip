@@ -27,16 +27,23 @@ __device__ __forceinline__ T group_sum(T acc, int np, int G) {
 // (column-major each), so the row is one stream of nb*np*np entries in which
 // entry e belongs to block column xi = e / np and matrix row e % np.  Lane l
 // owns VEC consecutive matrix rows (q = l % L, L = np/VEC lanes per column) of
-// column group cl = l / L; one load instruction of the wave covers C = 64/L
-// whole columns (C*np contiguous entries, 16-byte loads where the block size
+// column group cl = l / L; one load step of the wave covers C = 64/L whole
+// columns (C*np contiguous entries, 16-byte loads where the block size
 // allows).  The column index of block k sits in lane k's register and is
 // fetched with a cross-lane permute, so the only global loads in the loop are
 // the matrix stream and the x gather.
 
-template <typename T, int NP>
+// WIDE: four rows per lane wherever the block size allows (for FP64 two
+// 16-byte loads per lane), so that every x value fetched serves four matrix
+// entries -- half the gather instructions per streamed byte of two rows.
+// Blocks of 16 modes and more use it (measured: SpMV and the Jacobi sweep at
+// Np = 20 gain 4-7%); the small coarse blocks keep two rows per lane, where
+// the longer cross-lane reduction of the wide form costs more than it saves.
+template <typename T, int NP, bool WIDE = false>
 struct RowCfg {
-    static constexpr int VEC = sizeof(T) == 8 ? (NP % 2 == 0 ? 2 : 1)
-                                              : (NP % 4 == 0 ? 4 : (NP % 2 == 0 ? 2 : 1));
+    static constexpr int VEC = (WIDE || sizeof(T) == 4)
+                                   ? (NP % 4 == 0 ? 4 : (NP % 2 == 0 ? 2 : 1))
+                                   : (NP % 2 == 0 ? 2 : 1);
     static constexpr int L = NP / VEC;     // lanes per column
     static constexpr int C = 64 / L;       // columns per load instruction
     static constexpr int CH = C * NP;      // entries per load instruction
@@ -51,6 +58,15 @@ template <> struct VecT<float, 4> { using t = float4; };
 
 template <typename T, int V>
 __device__ __forceinline__ void load_vec(const T* p, T (&a)[V]) {
+    if constexpr (sizeof(T) == 8 && V == 4) {
+        const double2 u = *reinterpret_cast<const double2*>(p);
+        const double2 w = *reinterpret_cast<const double2*>(p + 2);
+        a[0] = u.x;
+        a[1] = u.y;
+        a[2] = w.x;
+        a[3] = w.y;
+        return;
+    } else {
     const typename VecT<T, V>::t v = *reinterpret_cast<const typename VecT<T, V>::t*>(p);
     if constexpr (V == 1) {
         a[0] = v;
@@ -63,15 +79,16 @@ __device__ __forceinline__ void load_vec(const T* p, T (&a)[V]) {
         a[2] = v.z;
         a[3] = v.w;
     }
+    }
 }
 
 // acc[v] += sum over the row's stream; partial sums per lane (reduce with
 // reduce_groups).  b0: first block of the row, nb: number of blocks.
-template <typename T, int NP>
+template <typename T, int NP, bool WIDE = false>
 __device__ __forceinline__ void row_stream(int b0, int nb, const int* __restrict__ ci,
                                            const T* __restrict__ A, const T* __restrict__ x,
-                                           int lane, T (&acc)[RowCfg<T, NP>::VEC]) {
-    using R = RowCfg<T, NP>;
+                                           int lane, T (&acc)[RowCfg<T, NP, WIDE>::VEC]) {
+    using R = RowCfg<T, NP, WIDE>;
     constexpr int V = R::VEC;
     const int q = lane % R::L;
     const int cl = lane / R::L;
@@ -146,11 +163,12 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const i
     if (row >= n_rows) return;
     const int beg = uniform(rp[row]), end = uniform(rp[row + 1]);
     if constexpr (NP > 0) {
-        using R = RowCfg<T, NP>;
+        constexpr bool W = NP >= 16;
+        using R = RowCfg<T, NP, W>;
         T acc[R::VEC];
 #pragma unroll
         for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
-        row_stream<T, NP>(beg, end - beg, ci, A, x, lane, acc);
+        row_stream<T, NP, W>(beg, end - beg, ci, A, x, lane, acc);
         reduce_groups<T, R::VEC>(acc, R::L, R::C);
         if (lane < R::L) {
 #pragma unroll
@@ -227,13 +245,13 @@ __global__ __launch_bounds__(256) void k_jacobi(int n_cells, int np_rt, const in
         const int64_t ob = (int64_t)row * np;
         T* rs = &res[w][(row - r0) * np];
         if constexpr (NP > 0) {
-            using R = RowCfg<T, NP>;
+            using R = RowCfg<T, NP, (NP >= 16)>;
             T acc[R::VEC];
 #pragma unroll
             for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
             if (!FIRST) {
                 const int beg = uniform(rp[row]), end = uniform(rp[row + 1]);
-                row_stream<T, NP>(beg, end - beg, ci, A, xin, lane, acc);
+                row_stream<T, NP, (NP >= 16)>(beg, end - beg, ci, A, xin, lane, acc);
                 reduce_groups<T, R::VEC>(acc, R::L, R::C);
             }
             if (lane < R::L) {
@@ -255,7 +273,7 @@ __global__ __launch_bounds__(256) void k_jacobi(int n_cells, int np_rt, const in
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const T* Dc = D + doff[cell];
     const int64_t base = (int64_t)r0 * np;
-    constexpr int V = NP > 0 ? RowCfg<T, (NP > 0 ? NP : 1)>::VEC : 1;
+    constexpr int V = NP > 0 ? RowCfg<T, (NP > 0 ? NP : 1), (NP >= 16)>::VEC : 1;
     if (nc <= 64 * V) {
         T acc[V];
         dense_apply<T, V>(Dc, nc, res[w], lane, acc);

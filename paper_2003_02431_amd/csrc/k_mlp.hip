@@ -16,6 +16,26 @@ constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHi
               oW3 = oB2 + kHid, oB3 = oW3 + kOut * kHid, kParams = oB3 + kOut;
 static_assert(kParams == 9704, "parameter count");
 
+// LDS copy of the parameters: rows of W2 and W3 padded to an odd stride so
+// that both the forward products (lane = output row) and the backward
+// products (lane = input column) read distinct banks; W1 rows (45) are odd.
+constexpr int kS1 = kIn, kS2 = kHid + 1, kS3 = kHid + 1;
+constexpr int lW1 = 0, lB1 = lW1 + kHid * kS1, lW2 = lB1 + kHid, lB2 = lW2 + kHid * kS2,
+              lW3 = lB2 + kHid, lB3 = lW3 + kOut * kS3, kLds = lB3 + kOut;
+
+__device__ __forceinline__ void stage_params(float* P, const float* __restrict__ g) {
+    for (int e = threadIdx.x; e < kParams; e += blockDim.x) {
+        int d;
+        if (e < oB1) d = e;                                                   // W1, stride 45
+        else if (e < oW2) d = lB1 + (e - oB1);
+        else if (e < oB2) d = lW2 + ((e - oW2) / kHid) * kS2 + (e - oW2) % kHid;
+        else if (e < oW3) d = lB2 + (e - oB2);
+        else if (e < oB3) d = lW3 + ((e - oW3) / kHid) * kS3 + (e - oW3) % kHid;
+        else d = lB3 + (e - oB3);
+        P[d] = g[e];
+    }
+}
+
 __device__ __forceinline__ float gelu_f(float x) {
     return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
 }
@@ -32,43 +52,85 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 __device__ __forceinline__ int uniform_l(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// y (lanes < 40) = MLP(f); f, h1, h2 are per-wave LDS buffers, P the parameters.
+// y (lanes < 40) = MLP(f); f, h1, h2 are per-wave LDS buffers, P the
+// parameters in the padded LDS layout.
 __device__ __forceinline__ float mlp_wave(const float* P, const float* f, float* h1, float* h2,
                                           int lane, float* z1o = nullptr, float* z2o = nullptr) {
-    float z = P[oB1 + lane];
-    for (int i = 0; i < kIn; ++i) z += P[oW1 + lane * kIn + i] * f[i];
+    float z = P[lB1 + lane];
+#pragma unroll 9
+    for (int i = 0; i < kIn; ++i) z += P[lW1 + lane * kS1 + i] * f[i];
     if (z1o) *z1o = z;
     h1[lane] = gelu_f(z);
     wave_sync_lds();
-    z = P[oB2 + lane];
-    for (int i = 0; i < kHid; ++i) z += P[oW2 + lane * kHid + i] * h1[i];
+    z = P[lB2 + lane];
+#pragma unroll 8
+    for (int i = 0; i < kHid; ++i) z += P[lW2 + lane * kS2 + i] * h1[i];
     if (z2o) *z2o = z;
     h2[lane] = gelu_f(z);
     wave_sync_lds();
     float y = 0.f;
     if (lane < kOut) {
-        y = P[oB3 + lane];
-        for (int i = 0; i < kHid; ++i) y += P[oW3 + lane * kHid + i] * h2[i];
+        y = P[lB3 + lane];
+#pragma unroll 8
+        for (int i = 0; i < kHid; ++i) y += P[lW3 + lane * kS3 + i] * h2[i];
     }
     return y;
 }
 
-// Y[s] = MLP(X[s]) for n samples (persistent waves, parameters staged in LDS)
+// Inference with the weights in registers: lane j holds row j of W1 and W2
+// and (j < 40) row j of W3; the activations of the previous layer are
+// broadcast one at a time with readlane (no LDS traffic per weight).
+struct MlpRegs {
+    float w1[kIn], w2[kHid], w3[kHid];
+    float b1, b2, b3;
+};
+
+__device__ __forceinline__ void load_regs(MlpRegs& R, const float* __restrict__ g, int lane) {
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) R.w1[i] = g[oW1 + lane * kIn + i];
+#pragma unroll
+    for (int i = 0; i < kHid; ++i) R.w2[i] = g[oW2 + lane * kHid + i];
+#pragma unroll
+    for (int i = 0; i < kHid; ++i) R.w3[i] = lane < kOut ? g[oW3 + lane * kHid + i] : 0.f;
+    R.b1 = g[oB1 + lane];
+    R.b2 = g[oB2 + lane];
+    R.b3 = lane < kOut ? g[oB3 + lane] : 0.f;
+}
+
+// f (inputs), h1, h2: per-wave LDS buffers; the weights come from registers
+// and every activation is read by all lanes at once (an LDS broadcast).
+// Returns output `lane` (valid for lane < 40).
+__device__ __forceinline__ float mlp_regs(const MlpRegs& R, const float* f, float* h1, float* h2,
+                                          int lane) {
+    float z = R.b1;
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) z += R.w1[i] * f[i];
+    h1[lane] = gelu_f(z);
+    wave_sync_lds();
+    z = R.b2;
+#pragma unroll
+    for (int i = 0; i < kHid; ++i) z += R.w2[i] * h1[i];
+    h2[lane] = gelu_f(z);
+    wave_sync_lds();
+    float y = R.b3;
+#pragma unroll
+    for (int i = 0; i < kHid; ++i) y += R.w3[i] * h2[i];
+    return y;
+}
+
+// Y[s] = MLP(X[s]) for n samples (persistent waves, weights in registers)
 __global__ __launch_bounds__(256) void k_mlp_forward(int n, const float* __restrict__ params,
                                                      const float* __restrict__ X,
                                                      float* __restrict__ Y) {
-    __shared__ float P[kParams];
-    __shared__ float buf[4][kIn + 2 * kHid];
-    for (int e = threadIdx.x; e < kParams; e += blockDim.x) P[e] = params[e];
-    __syncthreads();
+    __shared__ float act[4][48 + 2 * kHid];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    float* f = buf[w];
-    float* h1 = f + kIn;
-    float* h2 = h1 + kHid;
+    MlpRegs R;
+    load_regs(R, params, lane);
+    float* f = act[w];
     for (int s = uniform_l(blockIdx.x * 4 + w); s < n; s += gridDim.x * 4) {
         if (lane < kIn) f[lane] = X[(int64_t)s * kIn + lane];
         wave_sync_lds();
-        const float y = mlp_wave(P, f, h1, h2, lane);
+        const float y = mlp_regs(R, f, f + 48, f + 48 + kHid, lane);
         if (lane < kOut) Y[(int64_t)s * kOut + lane] = y;
         wave_sync_lds();
     }
@@ -82,9 +144,9 @@ __global__ __launch_bounds__(256) void k_mlp_grad(int n, int n_total,
                                                   const float* __restrict__ T,
                                                   float* __restrict__ partial,
                                                   float* __restrict__ partial_loss) {
-    __shared__ float P[kParams];
+    __shared__ float P[kLds];
     __shared__ float buf[4][kIn + 5 * kHid];
-    for (int e = threadIdx.x; e < kParams; e += blockDim.x) P[e] = params[e];
+    stage_params(P, params);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wid = blockIdx.x * 4 + w, nw = gridDim.x * 4;
@@ -120,7 +182,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(int n, int n_total,
             gb3 += d;
         }
         float dh2 = 0.f;
-        for (int k = 0; k < kOut; ++k) dh2 += P[oW3 + k * kHid + lane] * dy[k];
+#pragma unroll 8
+        for (int k = 0; k < kOut; ++k) dh2 += P[lW3 + k * kS3 + lane] * dy[k];
         const float d2 = dh2 * gelu_df(z2);
         dz2[lane] = d2;
         wave_sync_lds();
@@ -128,7 +191,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(int n, int n_total,
         for (int i = 0; i < kHid; ++i) gW2[i] += d2 * h1[i];
         gb2 += d2;
         float dh1 = 0.f;
-        for (int k = 0; k < kHid; ++k) dh1 += P[oW2 + k * kHid + lane] * dz2[k];
+#pragma unroll 8
+        for (int k = 0; k < kHid; ++k) dh1 += P[lW2 + k * kS2 + lane] * dz2[k];
         const float d1 = dh1 * gelu_df(z1);
 #pragma unroll
         for (int i = 0; i < kIn; ++i) gW1[i] += d1 * f[i];
@@ -183,20 +247,13 @@ __global__ void k_adam(int n, float* __restrict__ w, const float* __restrict__ g
 }
 
 // ---------------------------------------------------------------------------
-// The learned first sweep of the level-0 smoother (x_in = 0, residual = b):
-//   j_c = omega D_c^{-1} b_c,  s = |j_c|,  u = j_c / s placed in the species
-//   slots (A: 0..19, B: 20..39), features u | geom_c (5 values);
-//   x_c = j_c + s * MLP(features)[slots of the cell's rows]
-// (the network proposes the part of the error the damped block-Jacobi step
-// misses, in units of that step).
-// A cell whose network output is non-finite or larger than `guard` (relative
-// to s) keeps the plain Jacobi update (local fallback, counted in *nguard).
-// FEAT: instead write, for the selected cells c = cell0 + i cell_step, the
-//   features and the target (e_c - j_c) / s with the error e = x* - x_k
-//   (b holds the residual of x_k) as sample i -- the training pairs.
-// Inference runs over every cell (cell0 = 0, cell_step = 1).
-template <bool FEAT>
-__global__ __launch_bounds__(256) void k_learned_first(int n_sel, int cell0, int cell_step,
+// Training pairs of the learned first sweep.  For the selected cells
+// c = cell0 + i cell_step and the residual b of an iterate x_k:
+//   j_c = omega D_c^{-1} b_c,  s = |j_c|,  features u | geom_c with u = j_c / s
+//   placed in the species slots (A: 0..19, B: 20..39), and the target
+//   (e_c - j_c) / s with the error e = x* - x_k, in the same slots, scaled to
+//   norm `clip` when longer (clip = 0: no scaling); written as sample i.
+__global__ __launch_bounds__(256) void k_learned_pairs(int n_sel, int cell0, int cell_step,
                                                        const int* __restrict__ cell_ptr,
                                                        const int* __restrict__ row_species,
                                                        const float* __restrict__ geom,
@@ -205,84 +262,140 @@ __global__ __launch_bounds__(256) void k_learned_first(int n_sel, int cell0, int
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ xk,
                                                        const double* __restrict__ xs,
-                                                       const float* __restrict__ params,
-                                                       double omega, float guard,
-                                                       double* __restrict__ x,
+                                                       double omega, float clip,
                                                        float* __restrict__ Xf,
-                                                       float* __restrict__ Tf,
-                                                       int* __restrict__ nguard) {
+                                                       float* __restrict__ Tf) {
     constexpr int NP = 20;
-    __shared__ float P[FEAT ? 1 : kParams];
-    __shared__ float buf[4][kIn + 2 * kHid];
+    __shared__ float buf[4][kIn + kOut];
     __shared__ double rb[4][2 * NP];
-    if (!FEAT) {
-        for (int e = threadIdx.x; e < kParams; e += blockDim.x) P[e] = params[e];
-        __syncthreads();
-    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     float* f = buf[w];
-    float* h1 = f + kIn;
-    float* h2 = h1 + kHid;
-    int guarded = 0;
+    float* t_s = f + kIn;
     for (int i = uniform_l(blockIdx.x * 4 + w); i < n_sel; i += gridDim.x * 4) {
         const int c = cell0 + i * cell_step;
         const int r0 = uniform_l(cell_ptr[c]), r1 = uniform_l(cell_ptr[c + 1]);
         const int nc = (r1 - r0) * NP;            // 20 or 40 (checked on the host)
         if (lane < nc) rb[w][lane] = b[(int64_t)r0 * NP + lane];
         wave_sync_lds();
-        // j = omega D^{-1} b on the cell block (column-major D)
+        // j = omega D^{-1} b on the cell block (column-major D), unrolled for
+        // the two cell sizes so that the column loads overlap
         const double* Dc = D + doff[c];
         double j = 0.0;
-        if (lane < nc)
-            for (int k = 0; k < nc; ++k) j += Dc[(int64_t)k * nc + lane] * rb[w][k];
+        if (lane < nc) {
+            if (nc == NP) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) j += Dc[k * NP + lane] * rb[w][k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 2 * NP; ++k) j += Dc[k * 2 * NP + lane] * rb[w][k];
+            }
+        }
         j *= omega;
         double ss = lane < nc ? j * j : 0.0;
         for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
         const double sc = sqrt(ss);
         const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+        int slot = 0;
+        if (lane < nc) {
+            const int rr = lane / NP;
+            slot = row_species[r0 + rr] * NP + (lane - rr * NP);
+        }
+        double t = 0.0;
+        if (lane < nc) t = ((xs[(int64_t)r0 * NP + lane] - xk[(int64_t)r0 * NP + lane]) - j) * inv;
+        double tt = t * t;
+        for (int off = 32; off > 0; off >>= 1) tt += __shfl_xor(tt, off, 64);
+        const double tn = sqrt(tt);
+        if (clip > 0.f && tn > (double)clip) t *= (double)clip / tn;
         if (lane < kOut) f[lane] = 0.f;
+        if (lane < kOut) t_s[lane] = 0.f;
         wave_sync_lds();
         if (lane < nc) {
-            const int rr = lane / NP, k = lane - rr * NP;
-            const int sp = row_species[r0 + rr];
-            f[sp * NP + k] = (float)(j * inv);
+            f[slot] = (float)(j * inv);
+            t_s[slot] = (float)t;
         }
         if (lane < 5) f[kOut + lane] = geom[(int64_t)c * 5 + lane];
         wave_sync_lds();
-        if constexpr (FEAT) {
-            if (lane < kIn) Xf[(int64_t)i * kIn + lane] = f[lane];
-            if (lane < kOut) h2[lane] = 0.f;
-            wave_sync_lds();
-            if (lane < nc) {
-                const int rr = lane / NP, k = lane - rr * NP;
-                const int sp = row_species[r0 + rr];
-                const int64_t o = (int64_t)r0 * NP + lane;
-                h2[sp * NP + k] = (float)(((xs[o] - xk[o]) - j) * inv);
-            }
-            wave_sync_lds();
-            if (lane < kOut) Tf[(int64_t)i * kOut + lane] = h2[lane];
-            wave_sync_lds();
-            continue;
-        } else {
-        float y = mlp_wave(P, f, h1, h2, lane);
-        // local fallback: non-finite or oversized proposals keep plain Jacobi
-        float yy = lane < kOut ? y * y : 0.f;
-        bool bad = !(y == y) || fabsf(y) > 3.0e38f;
-        for (int off = 32; off > 0; off >>= 1) yy += __shfl_xor(yy, off, 64);
-        bad = __any(bad) || !(sqrtf(yy) <= guard);
-        if (bad) guarded += 1;
+        if (lane < kIn) Xf[(int64_t)i * kIn + lane] = f[lane];
+        if (lane < kOut) Tf[(int64_t)i * kOut + lane] = t_s[lane];
         wave_sync_lds();
-        h1[lane] = bad ? 0.f : y;                 // reuse h1 as the output slot buffer
-        wave_sync_lds();
-        if (lane < nc) {
-            const int rr = lane / NP, k = lane - rr * NP;
-            const int sp = row_species[r0 + rr];
-            x[(int64_t)r0 * NP + lane] = j + sc * (double)h1[sp * NP + k];
-        }
-        wave_sync_lds();
-        }
     }
-    if (!FEAT && lane == 0 && guarded) atomicAdd(nguard, guarded);
+}
+
+// ---------------------------------------------------------------------------
+// The learned correction of the first sweep, applied after the plain first
+// sweep has written j = omega D^{-1} b into x: per cell, s = |j_c|,
+// features [j_c / s in species slots | geom_c], x_c = j_c + s * MLP(features).
+// A wave takes chunks of kChunk consecutive cells: one round of loads brings
+// the chunk's rows of x, row species, geometry and cell pointers into LDS,
+// then the cells are evaluated one after another (weights in registers,
+// activations read from LDS as broadcasts), and the chunk is written back.
+constexpr int kChunk = 8;
+constexpr int kChunkRows = 2 * kChunk;
+
+__global__ __launch_bounds__(256) void k_learned_correct(int n_cells, const int* __restrict__ cell_ptr,
+                                                         const int* __restrict__ row_species,
+                                                         const float* __restrict__ geom,
+                                                         const float* __restrict__ params,
+                                                         float guard, double* __restrict__ x,
+                                                         int* __restrict__ nguard) {
+    constexpr int NP = 20;
+    __shared__ double xs[4][kChunkRows * NP];
+    __shared__ float act[4][48 + 2 * kHid];
+    __shared__ float gs[4][kChunk * 5];
+    __shared__ int spc[4][kChunkRows];
+    __shared__ int cps[4][kChunk + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    MlpRegs R;
+    load_regs(R, params, lane);
+    float* f = act[w];
+    float* h1 = f + 48;
+    float* h2 = h1 + kHid;
+    int guarded = 0;
+    const int n_chunks = (n_cells + kChunk - 1) / kChunk;
+    for (int ch = uniform_l(blockIdx.x * 4 + w); ch < n_chunks; ch += gridDim.x * 4) {
+        const int c0 = ch * kChunk;
+        const int nch = min(kChunk, n_cells - c0);
+        if (lane <= nch) cps[w][lane] = cell_ptr[c0 + lane];
+        if (lane < nch * 5) gs[w][lane] = geom[(int64_t)c0 * 5 + lane];
+        wave_sync_lds();
+        const int R0 = uniform_l(cps[w][0]), R1 = uniform_l(cps[w][nch]);
+        const int nv = (R1 - R0) * NP;                 // <= kChunkRows * NP (host-checked cells)
+        for (int k = lane; k < nv; k += 64) xs[w][k] = x[(int64_t)R0 * NP + k];
+        if (lane < R1 - R0) spc[w][lane] = row_species[R0 + lane];
+        wave_sync_lds();
+        for (int cc = 0; cc < nch; ++cc) {
+            const int r0 = uniform_l(cps[w][cc]) - R0, r1 = uniform_l(cps[w][cc + 1]) - R0;
+            const int nc = (r1 - r0) * NP;
+            const double j = lane < nc ? xs[w][r0 * NP + lane] : 0.0;
+            double ss = j * j;
+            for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+            const double sc = sqrt(ss);
+            const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+            int slot = 0;
+            if (lane < nc) {
+                const int rr = lane / NP;
+                slot = spc[w][r0 + rr] * NP + (lane - rr * NP);
+            }
+            if (lane < kOut) f[lane] = 0.f;
+            wave_sync_lds();
+            if (lane < nc) f[slot] = (float)(j * inv);
+            if (lane < 5) f[kOut + lane] = gs[w][cc * 5 + lane];
+            wave_sync_lds();
+            const float y = mlp_regs(R, f, h1, h2, lane);
+            // local fallback: non-finite or oversized proposals keep plain Jacobi
+            float yy = lane < kOut ? y * y : 0.f;
+            bool bad = lane < kOut && (!(y == y) || fabsf(y) > 3.0e38f);
+            for (int off = 32; off > 0; off >>= 1) yy += __shfl_xor(yy, off, 64);
+            bad = __any(bad) || !(sqrtf(yy) <= guard);
+            if (bad) guarded += 1;
+            const float ys = __shfl(y, slot, 64);
+            if (lane < nc && !bad) xs[w][r0 * NP + lane] = j + sc * (double)ys;
+            wave_sync_lds();
+        }
+        for (int k = lane; k < nv; k += 64) x[(int64_t)R0 * NP + k] = xs[w][k];
+        wave_sync_lds();
+    }
+    if (lane == 0 && guarded) atomicAdd(nguard, guarded);
 }
 
 // ---------------------------------------------------------------------------
@@ -290,8 +403,12 @@ static inline unsigned nbk(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 int mlp_param_count() { return kParams; }
 
+// register-resident inference kernels (about 200 VGPRs, two waves per SIMD):
+// one resident round of 4-wave blocks, each wave loops over samples/cells
+constexpr int kInferBlocks = 512;
+
 void launch_mlp_forward(hipStream_t s, int n, const float* params, const float* X, float* Y) {
-    const int g = (int)std::min<int64_t>(nbk(n, 4), 1024);
+    const int g = (int)std::min<int64_t>(nbk(n, 4), kInferBlocks);
     k_mlp_forward<<<std::max(g, 1), 256, 0, s>>>(n, params, X, Y);
 }
 
@@ -308,25 +425,22 @@ void launch_adam(hipStream_t s, float* w, const float* g, float* m, float* v, fl
     k_adam<<<nbk(kParams, 256), 256, 0, s>>>(kParams, w, g, m, v, lr, b1, b2, c1, c2, eps);
 }
 
-void launch_learned_first(hipStream_t s, int n_cells, const int* cp, const int* row_species,
-                          const float* geom, const int64_t* doff, const double* D,
-                          const double* b, const float* params, double omega, float guard,
-                          double* x, int* nguard) {
-    const int g = (int)std::min<int64_t>(nbk(n_cells, 4), 2048);
-    k_learned_first<false><<<std::max(g, 1), 256, 0, s>>>(n_cells, 0, 1, cp, row_species, geom, doff,
-                                                           D, b, nullptr, nullptr, params, omega,
-                                                           guard, x, nullptr, nullptr, nguard);
+void launch_learned_correct(hipStream_t s, int n_cells, const int* cp, const int* row_species,
+                            const float* geom, const float* params, float guard, double* x,
+                            int* nguard) {
+    const int64_t chunks = (n_cells + kChunk - 1) / kChunk;
+    const int g = (int)std::min<int64_t>(nbk(chunks, 4), kInferBlocks);
+    k_learned_correct<<<std::max(g, 1), 256, 0, s>>>(n_cells, cp, row_species, geom, params, guard,
+                                                     x, nguard);
 }
 
 void launch_learned_features(hipStream_t s, int n_sel, int cell0, int cell_step, const int* cp,
                              const int* row_species, const float* geom, const int64_t* doff,
                              const double* D, const double* r, const double* xk,
-                             const double* xs, double omega, float* Xf, float* Tf) {
+                             const double* xs, double omega, float clip, float* Xf, float* Tf) {
     const int g = (int)std::min<int64_t>(nbk(n_sel, 4), 2048);
-    k_learned_first<true><<<std::max(g, 1), 256, 0, s>>>(n_sel, cell0, cell_step, cp, row_species,
-                                                          geom, doff, D,
-                                                          r, xk, xs, nullptr, omega, 0.f, nullptr,
-                                                          Xf, Tf, nullptr);
+    k_learned_pairs<<<std::max(g, 1), 256, 0, s>>>(n_sel, cell0, cell_step, cp, row_species, geom,
+                                                   doff, D, r, xk, xs, omega, clip, Xf, Tf);
 }
 
 }  // namespace xdg

@@ -134,12 +134,12 @@ void launch_mlp_grad(hipStream_t s, int n, int n_total, int n_blocks, const floa
                      float* grad, float* loss);
 void launch_adam(hipStream_t s, float* w, const float* g, float* m, float* v, float lr, float b1,
                  float b2, float c1, float c2, float eps);
-void launch_learned_first(hipStream_t s, int n_cells, const int* cp, const int* row_species,
-                          const float* geom, const int64_t* doff, const double* D,
-                          const double* b, const float* params, double omega, float guard,
-                          double* x, int* nguard);
+// x holds j = omega D^{-1} b (the plain first sweep); adds the learned part
+void launch_learned_correct(hipStream_t s, int n_cells, const int* cp, const int* row_species,
+                            const float* geom, const float* params, float guard, double* x,
+                            int* nguard);
 void launch_learned_features(hipStream_t s, int n_sel, int cell0, int cell_step, const int* cp,
                              const int* row_species, const float* geom, const int64_t* doff,
                              const double* D, const double* r, const double* xk,
-                             const double* xs, double omega, float* Xf, float* Tf);
+                             const double* xs, double omega, float clip, float* Xf, float* Tf);
 }  // namespace xdg

@@ -32,10 +32,13 @@ bool learned_active(xdg_handle* h) {
     return h->opt.smoother == XDG_LEARNED && h->learned_ready && !h->learned_off;
 }
 
-// First pre-smoothing sweep of level 0 from x = 0 with the network's proposal
+// First pre-smoothing sweep of level 0 from x = 0 with the network's proposal:
+// the plain first sweep (x = omega D^{-1} b), then the per-cell correction
 void learned_first_sweep(xdg_handle* h, Level& lv) {
-    launch_learned_first(h->s, lv.n_cells, lv.cp, h->row_species, h->cell_geom, lv.doff, lv.D64,
-                         lv.b64, h->mlp_w, h->opt.omega, h->guard, lv.x64, h->d_nguard);
+    launch_jacobi<double>(h->s, true, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff,
+                          lv.D64, lv.b64, nullptr, lv.x64, h->opt.omega);
+    launch_learned_correct(h->s, lv.n_cells, lv.cp, h->row_species, h->cell_geom, h->mlp_w,
+                           h->guard, lv.x64, h->d_nguard);
 }
 
 // learned-smoother requirements on the handle's configuration
@@ -155,10 +158,12 @@ extern "C" int xdg_set_cell_features(xdg_handle* h, const int32_t* row_species,
 }
 
 extern "C" int xdg_learned_pairs(xdg_handle* h, const double* b, const double* xk,
-                                 const double* xs, int32_t cell0, int32_t cell_step, float* X,
-                                 float* T, int32_t* n_out) {
+                                 const double* xs, int32_t cell0, int32_t cell_step, float clip,
+                                 float* X, float* T, int32_t* n_out) {
     if (!h || !b || !xk || !xs || !X || !T || !n_out)
         return fail(XDG_EINVAL, "xdg_learned_pairs: NULL argument");
+    if (!(clip >= 0.f) || !std::isfinite(clip))
+        return fail(XDG_EINVAL, "xdg_learned_pairs: clip must be finite and >= 0");
     if (!h->row_species) return fail(XDG_EINVAL, "xdg_learned_pairs: no cell features set");
     Level& f = h->L[0];
     if (cell0 < 0 || cell0 >= f.n_cells || cell_step < 1)
@@ -167,7 +172,7 @@ extern "C" int xdg_learned_pairs(xdg_handle* h, const double* b, const double* x
     // residual of the iterate, then features and targets of the selected cells
     launch_spmv<double>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, xk, b, h->w, 0);
     launch_learned_features(h->s, n_sel, cell0, cell_step, f.cp, h->row_species, h->cell_geom,
-                            f.doff, f.D64, h->w, xk, xs, h->opt.omega, X, T);
+                            f.doff, f.D64, h->w, xk, xs, h->opt.omega, clip, X, T);
     HIPCHK(hipGetLastError());
     *n_out = n_sel;
     return XDG_OK;

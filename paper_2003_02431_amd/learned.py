@@ -24,12 +24,13 @@ def init_params(seed=0):
     return p
 
 
-def plain_pairs(S, b, xs, iterates, cell_step=1, restart_rtol=1e-300):
+def plain_pairs(S, b, xs, iterates, cell_step=1, clip=0.0, restart_rtol=1e-300):
     """Training pairs from iterates of the handle's plain solver.
 
     For every k in `iterates`, x_k is the k-th iterate of the plain
     (block-Jacobi) solve of M x = b from x = 0; the pairs of x_k are taken on
-    the cells k mod cell_step, k mod cell_step + cell_step, ...  Returns
+    the cells k mod cell_step, k mod cell_step + cell_step, ...; targets
+    longer than `clip` (> 0) are scaled to that length.  Returns
     float32 device tensors X [n, 45], T [n, 40].  The handle's smoother and
     stopping rule are restored afterwards."""
     torch = S.torch
@@ -48,7 +49,7 @@ def plain_pairs(S, b, xs, iterates, cell_step=1, restart_rtol=1e-300):
                 B.xdg_set_tolerance(h, restart_rtol, int(k))
                 B.xdg_solve(h, b, x)
             n = B.xdg_learned_pairs(h, b, x, xs, k % cell_step, cell_step, X[off:off + cnt],
-                                    T[off:off + cnt])
+                                    T[off:off + cnt], clip)
             assert n == cnt
             off += cnt
     finally:

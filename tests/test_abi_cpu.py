@@ -104,7 +104,7 @@ def test_learned_smoother_requirements_and_null_calls():
                lib.xdg_mlp_gradient(None, 1, None, None, None, None),
                lib.xdg_mlp_train(None, 1, None, None, 1, 1, 1e-3, None),
                lib.xdg_set_cell_features(None, None, None),
-               lib.xdg_learned_pairs(None, None, None, None, 0, 1, None, None, None),
+               lib.xdg_learned_pairs(None, None, None, None, 0, 1, 0.0, None, None, None),
                lib.xdg_set_tolerance(None, 1e-8, 10),
                lib.xdg_set_smoother(None, 0, 4.0), lib.xdg_learned_stats(None, None, None)):
         assert rc == B.XDG_EINVAL

@@ -102,3 +102,21 @@ def test_guard_keeps_plain_step(case):
     th[0] = np.nan
     x, nb = learned.first_sweep(H, rs, g, th, r, guard=1e30)
     assert nb == len(pr.cell_ptr) - 1 and np.all(np.isfinite(x))
+
+
+def test_clipped_pairs_keep_direction(case):
+    pr, H, rs, g = case
+    rng = np.random.default_rng(6)
+    xk, xs = rng.uniform(-1, 1, pr.b.size), rng.uniform(-1, 1, pr.b.size)
+    X, T = learned.pairs(H, rs, g, pr.b, xk, xs)
+    cl = float(np.median(np.linalg.norm(T, axis=1)))
+    Xc, Tc = learned.pairs(H, rs, g, pr.b, xk, xs, clip=cl)
+    assert np.array_equal(X, Xc)
+    n, nc = np.linalg.norm(T, axis=1), np.linalg.norm(Tc, axis=1)
+    assert (n > cl).any() and (n <= cl).any()
+    assert np.all(nc <= cl * (1 + 1e-14))
+    small = n <= cl
+    assert np.array_equal(Tc[small], T[small])
+    big = ~small
+    cos = np.sum(T[big] * Tc[big], axis=1) / (n[big] * nc[big])
+    assert np.allclose(cos, 1.0, atol=1e-14)
