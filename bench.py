@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the level-0 SpMV from the FETCH_SIZE / WRITE_SIZE
 # counter passes (scaled by a plain copy of known size), valid only for the
 # kernel source they were taken on.
-SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "a437c2aae3476641", "bytes": 771.6e6,
+SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "19fb7626eff43065", "bytes": 771.1e6,
                 "summary": "profiles/k_bsr_spmv_f64_np20_32cubed_hbm_counters.md"}
 
 
@@ -438,8 +438,9 @@ def main():
             torch.cuda.synchronize()
             tm.append(time.perf_counter() - t2)
         errm = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
-        # the same form run until its solution error is <= 1e-8 (rel.res 1e-9)
-        B.xdg_set_tolerance(Sm.h, 1e-9, 1000)
+        # the same form run until its solution error is <= 1e-8: FGMRES minimises
+        # the residual, not the energy error, and needs rel.res 1e-10 for that
+        B.xdg_set_tolerance(Sm.h, 1e-10, 1000)
         te = []
         for _ in range(3):
             xm.zero_()
@@ -452,7 +453,7 @@ def main():
         erre = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
         mixed = dict(time_s=round(float(np.median(tm)), 5), iters=itm, relres=frm,
                      err_vs_fp64=errm, krylov="FGMRES(30)",
-                     at_err_1e_8=dict(rtol=1e-9, time_s=round(float(np.median(te)), 5),
+                     at_err_1e_8=dict(rtol=1e-10, time_s=round(float(np.median(te)), 5),
                                       iters=ite, relres=fre, err_vs_fp64=erre),
                      note="FP32 V-cycle (A, D^-1, R in FP32), FP64 Arnoldi, SpMV in "
                           "Arnoldi, residuals and coarsest inverse")
