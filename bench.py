@@ -451,15 +451,38 @@ def main():
             torch.cuda.synchronize()
             te.append(time.perf_counter() - t2)
         erre = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
+        Sm.close()
+        # FP32 V-cycle inside flexible CG to rel.res 1e-8
+        Sc = B.Solver(pr, B.options(krylov=B.XDG_CG, precision=B.XDG_MIXED, rtol=1e-8,
+                                    maxit=1000))
+        xc = Sc.vec(0)
+        B.xdg_update_matrix(Sc.h, val_dev)
+        B.xdg_solve(Sc.h, b_dev, xc, hist_cap=2000)     # warm-up
+        tc = []
+        for _ in range(3):
+            xc.zero_()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            B.xdg_update_matrix(Sc.h, val_dev)
+            rcc, itc, frc, _ = B.xdg_solve(Sc.h, b_dev, xc, hist_cap=2000)
+            torch.cuda.synchronize()
+            tc.append(time.perf_counter() - t2)
+        errc = float(torch.linalg.norm(xc - xt) / torch.linalg.norm(xt))
+        Sc.close()
+        log(f"[bench] mixed flexible CG: {tc} iters {itc} relres {frc:.2e} err {errc:.2e}")
         mixed = dict(time_s=round(float(np.median(tm)), 5), iters=itm, relres=frm,
                      err_vs_fp64=errm, krylov="FGMRES(30)",
                      at_err_1e_8=dict(rtol=1e-10, time_s=round(float(np.median(te)), 5),
                                       iters=ite, relres=fre, err_vs_fp64=erre),
+                     flexible_cg=dict(rtol=1e-8, time_s=round(float(np.median(tc)), 5),
+                                      iters=itc, relres=frc, err_vs_fp64=errc,
+                                      speedup_vs_fp64_cg=round(dt / float(np.median(tc)), 3)),
                      note="FP32 V-cycle (A, D^-1, R in FP32), FP64 Arnoldi, SpMV in "
-                          "Arnoldi, residuals and coarsest inverse")
+                          "Arnoldi, residuals and coarsest inverse; flexible_cg: the same "
+                          "FP32 V-cycle inside flexible CG with FP64 residuals, directions "
+                          "and inner products")
         log(f"[bench] mixed: {tm} iters {itm} relres {frm:.2e} err {errm:.2e}; "
             f"to err<=1e-8: {te} iters {ite} err {erre:.2e}")
-        Sm.close()
 
     # roofline of the level-0 block SpMV
     t_spmv = time_spmv(torch, B, S, 0)

@@ -83,7 +83,7 @@ typedef struct {
 } xdg_transfer;
 
 typedef struct {
-    int32_t krylov;           /* XDG_CG (needs precision XDG_FP64) | XDG_FGMRES */
+    int32_t krylov;           /* XDG_CG (flexible CG with XDG_MIXED) | XDG_FGMRES */
     int32_t restart;          /* FGMRES restart length (<= 64)                  */
     int32_t maxit;            /* Krylov iteration limit                         */
     int32_t nu_pre, nu_post;  /* block-Jacobi sweeps per level                  */

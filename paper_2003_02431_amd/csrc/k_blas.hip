@@ -59,6 +59,15 @@ __global__ void k_cg_update_p(int64_t n, const double* __restrict__ scal, int i_
     p[i] = z[i] + beta * p[i];
 }
 
+// flexible CG direction: p = z - (scal[i_zq] / scal[i_pq]) p
+__global__ void k_fcg_update_p(int64_t n, const double* __restrict__ scal, int i_zq, int i_pq,
+                               const double* __restrict__ z, double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double beta = scal[i_zq] / scal[i_pq];
+    p[i] = z[i] - beta * p[i];
+}
+
 __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] += a * x[i];
@@ -82,6 +91,10 @@ void launch_cg_update_xr(hipStream_t s, int64_t n, const double* scal, int i_rz,
 void launch_cg_update_p(hipStream_t s, int64_t n, const double* scal, int i_new, int i_old,
                         const double* z, double* p) {
     k_cg_update_p<<<nblk(n, 256), 256, 0, s>>>(n, scal, i_new, i_old, z, p);
+}
+void launch_fcg_update_p(hipStream_t s, int64_t n, const double* scal, int i_zq, int i_pq,
+                         const double* z, double* p) {
+    k_fcg_update_p<<<nblk(n, 256), 256, 0, s>>>(n, scal, i_zq, i_pq, z, p);
 }
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
     k_axpy<<<nblk(n, 256), 256, 0, s>>>(n, a, x, y);

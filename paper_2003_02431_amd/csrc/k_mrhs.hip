@@ -421,19 +421,32 @@ __global__ __launch_bounds__(256) void k_multidot16_partial(int64_t n16, int nv,
                                                             const TV* __restrict__ V,
                                                             const double* __restrict__ w,
                                                             double* __restrict__ partial) {
-    __shared__ double sh[256];
-    for (int k = 0; k < nv; ++k) {
-        const TV* v = V + (int64_t)k * n16;
-        double acc = 0.0;
+    // groups of kG basis vectors share one pass over w (read once per group,
+    // not once per vector); per-thread sums in registers, then a fixed-order
+    // block reduction per (vector, column)
+    constexpr int kG = 16;
+    __shared__ double sh[kG][256];
+    for (int k0 = 0; k0 < nv; k0 += kG) {
+        const int g = min(kG, nv - k0);
+        double acc[kG];
+#pragma unroll
+        for (int q = 0; q < kG; ++q) acc[q] = 0.0;
         for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n16;
-             e += (int64_t)gridDim.x * 256)
-            acc += (double)v[e] * w[e];
-        sh[threadIdx.x] = acc;
+             e += (int64_t)gridDim.x * 256) {
+            const double wv = w[e];
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (q < g) acc[q] += (double)V[(int64_t)(k0 + q) * n16 + e] * wv;
+        }
+#pragma unroll
+        for (int q = 0; q < kG; ++q) sh[q][threadIdx.x] = acc[q];
         __syncthreads();
-        if (threadIdx.x < 16) {
+        // thread t < 16 g: vector k0 + t / 16, column t % 16
+        if (threadIdx.x < 16 * g) {
+            const int q = threadIdx.x >> 4, c = threadIdx.x & 15;
             double s = 0.0;
-            for (int t = threadIdx.x; t < 256; t += 16) s += sh[t];
-            partial[((int64_t)k * gridDim.x + blockIdx.x) * 16 + threadIdx.x] = s;
+            for (int t = c; t < 256; t += 16) s += sh[q][t];
+            partial[((int64_t)(k0 + q) * gridDim.x + blockIdx.x) * 16 + c] = s;
         }
         __syncthreads();
     }

@@ -329,8 +329,6 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     CHK(xdg::learned_validate(opt, A0->np));
     if (opt->krylov == XDG_FGMRES && (opt->restart < 1 || opt->restart > 64))
         return fail(XDG_EINVAL, "xdg_create: FGMRES restart must be in [1, 64]");
-    if (opt->krylov == XDG_CG && opt->precision != XDG_FP64)
-        return fail(XDG_EINVAL, "xdg_create: CG needs the FP64 (symmetric) preconditioner");
     if (opt->krylov == XDG_CG && opt->nu_pre != opt->nu_post)
         return fail(XDG_EINVAL, "xdg_create: CG needs nu_pre == nu_post (symmetric V-cycle)");
     if (opt->nrhs == kNrhs) CHK(mrhs_validate(opt, A0->np, T, n_levels));
@@ -591,6 +589,12 @@ static int true_relres(xdg_handle* h, const double* b, const double* x, double* 
     return XDG_OK;
 }
 
+// Preconditioned CG.  With the FP32 V-cycle (precision XDG_MIXED) the
+// preconditioner is symmetric only up to FP32 rounding, so the flexible
+// variant is used (Notay's FCG with one stored direction): alpha = p.r / p.q
+// and the new direction is made A-orthogonal to the previous one,
+// beta = -z.q_old / p_old.q_old; in exact arithmetic with a fixed symmetric
+// preconditioner it is PCG.
 static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int cap,
                     int* iters) {
     Level& f = h->L[0];
@@ -611,13 +615,15 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
     if (cap > 0) hist[0] = rel;
     *iters = 0;
     if (rel <= h->opt.rtol) return XDG_OK;
+    const bool flex = h->mixed;
     CHK(apply_precond(h, h->r, h->z));
     HIPCHK(hipMemcpyAsync(h->p, h->z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     int cur = S_RZ0, nxt = S_RZ1;
-    launch_dot(s, n, h->r, h->z, h->part, h->scal + cur);
+    if (!flex) launch_dot(s, n, h->r, h->z, h->part, h->scal + cur);
     for (int k = 1; k <= h->opt.maxit; ++k) {
         launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, h->p, nullptr, h->q, 0);
         launch_dot(s, n, h->p, h->q, h->part, h->scal + S_PQ);
+        if (flex) launch_dot(s, n, h->p, h->r, h->part, h->scal + cur);   // alpha numerator
         launch_cg_update_xr(s, n, h->scal, cur, S_PQ, h->p, h->q, x, h->r);
         launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
         CHK(read_scalars(h, S_RR, 2));
@@ -629,9 +635,14 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
         if (k < cap) hist[k] = rel;
         if (rel <= h->opt.rtol) return XDG_OK;
         CHK(apply_precond(h, h->r, h->z));
-        launch_dot(s, n, h->r, h->z, h->part, h->scal + nxt);
-        launch_cg_update_p(s, n, h->scal, nxt, cur, h->z, h->p);
-        std::swap(cur, nxt);
+        if (flex) {
+            launch_dot(s, n, h->z, h->q, h->part, h->scal + nxt);
+            launch_fcg_update_p(s, n, h->scal, nxt, S_PQ, h->z, h->p);
+        } else {
+            launch_dot(s, n, h->r, h->z, h->part, h->scal + nxt);
+            launch_cg_update_p(s, n, h->scal, nxt, cur, h->z, h->p);
+            std::swap(cur, nxt);
+        }
     }
     return XDG_ENOCONV;
 }

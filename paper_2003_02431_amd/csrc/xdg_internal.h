@@ -70,6 +70,8 @@ void launch_cg_update_xr(hipStream_t s, int64_t n, const double* scal, int i_rz,
                          const double* p, const double* q, double* x, double* r);
 void launch_cg_update_p(hipStream_t s, int64_t n, const double* scal, int i_new, int i_old,
                         const double* z, double* p);
+void launch_fcg_update_p(hipStream_t s, int64_t n, const double* scal, int i_zq, int i_pq,
+                         const double* z, double* p);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);
 void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y);
 

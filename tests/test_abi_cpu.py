@@ -51,7 +51,7 @@ def test_create_rejects_invalid_input(mutate, needle):
 def test_create_rejects_bad_options():
     from paper_2003_02431_amd import binding as B
     rp, ci, val, cp = _tiny()
-    for opt in (B.options(omega=2.5), B.options(krylov=B.XDG_CG, precision=B.XDG_MIXED),
+    for opt in (B.options(omega=2.5), B.options(precision=7),
                 B.options(krylov=B.XDG_FGMRES, restart=0), B.options(nu_pre=2, nu_post=1),
                 B.options(rtol=0.0), B.options(nrhs=2)):
         with pytest.raises(B.XdgError) as e:

@@ -208,6 +208,30 @@ def test_fgmres_solve(name, prec, torch):
     S.close()
 
 
+@pytest.mark.parametrize("name", ["c1", "c2n16"])
+def test_mixed_flexible_cg(name, torch):
+    """FP32 V-cycle inside flexible CG (FP64 residuals, directions and inner
+    products): the error against the oracle's x* follows the energy-norm
+    minimisation of CG, so rel.res 1e-8 already gives error <= 1e-8."""
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    pr, H, _ = _case(name, torch)
+    rtol = 1e-8
+    S = B.Solver(pr, B.options(krylov=B.XDG_CG, precision=B.XDG_MIXED, rtol=rtol, maxit=600))
+    xs, _, ito = mg.pcg(H.A[0], pr.b, H.vcycle, rtol=1e-13, maxit=1000)
+    _, _, it8 = mg.pcg(H.A[0], pr.b, H.vcycle, rtol=rtol, maxit=1000)
+    x = S.vec(0)
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0, pr.b), x)
+    xg = x.cpu().numpy()
+    tr = np.linalg.norm(pr.b - H.A[0] @ xg) / np.linalg.norm(pr.b)
+    err = _rel(xg, xs)
+    _log(f"  {name} flexible CG mixed: it={it} (oracle FP64 PCG {it8}) relres={tr:.2e} "
+         f"err vs x*={err:.2e}")
+    assert rc == 0 and tr <= 1.05 * rtol and abs(fr - tr) <= 1e-3 * tr
+    assert err <= 1e-8
+    S.close()
+
+
 def test_mixed_vcycle_is_fp32(torch):
     """The mixed handle's V-cycle runs in FP32: it differs from the FP64 cycle
     by FP32 rounding, not by zero and not by more."""
