@@ -138,6 +138,47 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(int n_rows, const int* __rest
     }
 }
 
+// X_out[I_c] = X_in[I_c] + omega D_c^{-1} res for a cell block of compile-time
+// order NC (packed row-tiled D, res [NC][16] in LDS): every D operand of the
+// block is loaded before the MFMAs so the loads overlap.
+template <int NC, bool FIRST>
+__device__ __forceinline__ void cell_apply_mrhs(const float* __restrict__ D, const float* res,
+                                                int lane, int64_t base,
+                                                const float* __restrict__ Xin,
+                                                float* __restrict__ Xout, float omega) {
+    constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4;
+    const int li = lane & 15, lk = lane >> 4;
+    float av[KT][MT], rv[KT];
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk) {
+        const int k = 4 * kk + lk;
+        const bool kv = k < NC;
+        rv[kk] = kv ? res[k * 16 + li] : 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int nr = tile_rows(NC, m);
+            av[kk][m] = (kv && li < nr) ? D[16 * m * NC + nr * k + li] : 0.f;
+        }
+    }
+    f32x4 acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = Mfma<float>::mma(av[kk][m], rv[kk], acc[m]);
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * m + Mfma<float>::row(lk, r);
+            if (i < NC) {
+                const int64_t o = base + (int64_t)i * 16 + li;
+                Xout[o] = (FIRST ? 0.f : Xin[o]) + omega * acc[m][r];
+            }
+        }
+}
+
 // One damped block-Jacobi sweep on 16 columns, FP32, MFMA for both the
 // residual rows and the cell-block inverse (packed, order n_c):
 //   X_out[I_c] = X_in[I_c] + omega D_c^{-1} (B - M X_in)[I_c]
@@ -184,33 +225,39 @@ __global__ __launch_bounds__(256) void k_jacobi_mrhs(int n_cells, const int* __r
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const float* D = Dp + doff[cell];
-    const int mtd = (nc + 15) / 16, ktd = (nc + 3) / 4;
-    f32x4 acc[MTD];
+    const int64_t base = (int64_t)r0 * NP * 16;
+    if (nc == NP) {
+        cell_apply_mrhs<NP, FIRST>(D, res[w], lane, base, Xin, Xout, omega);
+    } else if (nc == 2 * NP) {
+        cell_apply_mrhs<2 * NP, FIRST>(D, res[w], lane, base, Xin, Xout, omega);
+    } else {
+        const int mtd = (nc + 15) / 16, ktd = (nc + 3) / 4;
+        f32x4 acc[MTD];
 #pragma unroll
-    for (int m = 0; m < MTD; ++m) acc[m] = f32x4{0, 0, 0, 0};
-    for (int kk = 0; kk < ktd; ++kk) {
-        const int k = 4 * kk + lk;
-        const bool kv = k < nc;
-        const float rv = kv ? res[w][k * 16 + li] : 0.f;
+        for (int m = 0; m < MTD; ++m) acc[m] = f32x4{0, 0, 0, 0};
+        for (int kk = 0; kk < ktd; ++kk) {
+            const int k = 4 * kk + lk;
+            const bool kv = k < nc;
+            const float rv = kv ? res[w][k * 16 + li] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MTD; ++m) {
+                if (m < mtd) {
+                    const int nr = tile_rows(nc, m);
+                    const float av = (kv && li < nr) ? D[16 * m * nc + nr * k + li] : 0.f;
+                    acc[m] = Mfma<float>::mma(av, rv, acc[m]);
+                }
+            }
+        }
 #pragma unroll
         for (int m = 0; m < MTD; ++m) {
             if (m < mtd) {
-                const int nr = tile_rows(nc, m);
-                const float av = (kv && li < nr) ? D[16 * m * nc + nr * k + li] : 0.f;
-                acc[m] = Mfma<float>::mma(av, rv, acc[m]);
-            }
-        }
-    }
-    const int64_t base = (int64_t)r0 * NP * 16;
 #pragma unroll
-    for (int m = 0; m < MTD; ++m) {
-        if (m < mtd) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * m + Mfma<float>::row(lk, r);
-                if (i < nc) {
-                    const int64_t o = base + (int64_t)i * 16 + li;
-                    Xout[o] = (FIRST ? 0.f : Xin[o]) + omega * acc[m][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * m + Mfma<float>::row(lk, r);
+                    if (i < nc) {
+                        const int64_t o = base + (int64_t)i * 16 + li;
+                        Xout[o] = (FIRST ? 0.f : Xin[o]) + omega * acc[m][r];
+                    }
                 }
             }
         }
@@ -416,61 +463,114 @@ namespace xdg {
 
 // ---- 16-column vector kernels: column c of element e is e % 16 ------------
 // partial[(k * gridDim + blk) * 16 + c] = sum over the block's slice of V_k * w
+template <typename TV> struct Vec4;
+template <> struct Vec4<float> {
+    static __device__ __forceinline__ void load(const float* p, double (&v)[4]) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+};
+template <> struct Vec4<double> {
+    static __device__ __forceinline__ void load(const double* p, double (&v)[4]) {
+        const double2 t0 = *reinterpret_cast<const double2*>(p);
+        const double2 t1 = *reinterpret_cast<const double2*>(p + 2);
+        v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
+    }
+};
+
+// partial[k][block][c] = sum over this block's elements e (column c = e % 16)
+// of V_k[e] w[e].  Every thread takes 4 consecutive elements per step (16-byte
+// loads; since the grid stride is a multiple of 16 a thread always sees the
+// same 4 columns), and groups of kG basis vectors share one pass over w.
+// Fixed-order sums: per thread ascending e, then a fixed block reduction.
 template <typename TV>
 __global__ __launch_bounds__(256) void k_multidot16_partial(int64_t n16, int nv,
                                                             const TV* __restrict__ V,
                                                             const double* __restrict__ w,
                                                             double* __restrict__ partial) {
-    // groups of kG basis vectors share one pass over w (read once per group,
-    // not once per vector); per-thread sums in registers, then a fixed-order
-    // block reduction per (vector, column)
-    constexpr int kG = 16;
-    __shared__ double sh[kG][256];
+    constexpr int kG = 8;
+    __shared__ double sh[4][kG][16];
+    const int64_t n4 = n16 >> 2;
+    const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
     for (int k0 = 0; k0 < nv; k0 += kG) {
         const int g = min(kG, nv - k0);
-        double acc[kG];
+        double acc[kG][4];
 #pragma unroll
-        for (int q = 0; q < kG; ++q) acc[q] = 0.0;
-        for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n16;
-             e += (int64_t)gridDim.x * 256) {
-            const double wv = w[e];
+        for (int q = 0; q < kG; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[q][i] = 0.0;
+        for (int64_t e4 = (int64_t)blockIdx.x * 256 + threadIdx.x; e4 < n4;
+             e4 += (int64_t)gridDim.x * 256) {
+            double wv[4];
+            Vec4<double>::load(w + 4 * e4, wv);
 #pragma unroll
             for (int q = 0; q < kG; ++q)
-                if (q < g) acc[q] += (double)V[(int64_t)(k0 + q) * n16 + e] * wv;
-        }
+                if (q < g) {
+                    double vv[4];
+                    Vec4<TV>::load(V + (int64_t)(k0 + q) * n16 + 4 * e4, vv);
 #pragma unroll
-        for (int q = 0; q < kG; ++q) sh[q][threadIdx.x] = acc[q];
+                    for (int i = 0; i < 4; ++i) acc[q][i] += vv[i] * wv[i];
+                }
+        }
+        // lanes with the same lane % 4 hold the same 4 columns: fixed xor tree
+        // over the other lane bits, then lanes 0..3 hold the wave's sums
+#pragma unroll
+        for (int q = 0; q < kG; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double v = acc[q][i];
+                for (int off = 4; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+                if (lane < 4) sh[wv_id][q][4 * lane + i] = v;
+            }
         __syncthreads();
-        // thread t < 16 g: vector k0 + t / 16, column t % 16
         if (threadIdx.x < 16 * g) {
             const int q = threadIdx.x >> 4, c = threadIdx.x & 15;
-            double s = 0.0;
-            for (int t = c; t < 256; t += 16) s += sh[q][t];
+            const double s = ((sh[0][q][c] + sh[1][q][c]) + sh[2][q][c]) + sh[3][q][c];
             partial[((int64_t)(k0 + q) * gridDim.x + blockIdx.x) * 16 + c] = s;
         }
         __syncthreads();
     }
 }
 
-__global__ void k_multidot16_final(int nv, int nb, const double* __restrict__ partial,
-                                   double* __restrict__ out) {
-    const int k = blockIdx.x, c = threadIdx.x;
-    if (k >= nv || c >= 16) return;
+// out[k][c] = sum over the nb block partials, in a fixed order: thread
+// t = 16 j + c sums blocks j, j + 16, ... of column c, then thread c adds the
+// 16 part sums in order
+__global__ __launch_bounds__(256) void k_multidot16_final(int nv, int nb,
+                                                          const double* __restrict__ partial,
+                                                          double* __restrict__ out) {
+    __shared__ double sh[256];
+    const int k = blockIdx.x, c = threadIdx.x & 15, j = threadIdx.x >> 4;
+    if (k >= nv) return;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[((int64_t)k * nb + b) * 16 + c];
-    out[k * 16 + c] = s;
+    for (int b = j; b < nb; b += 16) s += partial[((int64_t)k * nb + b) * 16 + c];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += sh[q * 16 + c];
+        out[k * 16 + c] = t;
+    }
 }
 
-// w[e] -/+= sum_k coef[k][e % 16] V_k[e]
+// w[e] -/+= sum_k coef[k][e % 16] V_k[e]; 4 consecutive elements per thread
 template <typename TV, typename TW, bool NEG>
 __global__ void k_multi_axpy16(int64_t n16, int nv, const TV* __restrict__ V,
                                const double* __restrict__ coef, TW* __restrict__ w) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n16) return;
-    const int c = (int)(e & 15);
-    double acc = 0.0;
-    for (int k = 0; k < nv; ++k) acc += coef[k * 16 + c] * (double)V[(int64_t)k * n16 + e];
-    w[e] = NEG ? (TW)((double)w[e] - acc) : (TW)((double)w[e] + acc);
+    const int64_t e4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (4 * e4 >= n16) return;
+    const int c0 = (int)((4 * e4) & 15);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nv; ++k) {
+        double vv[4];
+        Vec4<TV>::load(V + (int64_t)k * n16 + 4 * e4, vv);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += coef[k * 16 + c0 + i] * vv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t e = 4 * e4 + i;
+        w[e] = NEG ? (TW)((double)w[e] - acc[i]) : (TW)((double)w[e] + acc[i]);
+    }
 }
 
 // out[e] = w[e] * s[e % 16]
@@ -484,14 +584,14 @@ __global__ void k_scale16(int64_t n16, const double* __restrict__ w, const doubl
 template <typename TV>
 void launch_multidot16(hipStream_t s, int64_t n16, int nv, const TV* V, const double* w,
                        double* partial, double* out) {
-    k_multidot16_partial<TV><<<kDotBlocks, 256, 0, s>>>(n16, nv, V, w, partial);
-    k_multidot16_final<<<nv, 16, 0, s>>>(nv, kDotBlocks, partial, out);
+    k_multidot16_partial<TV><<<kDot16Blocks, 256, 0, s>>>(n16, nv, V, w, partial);
+    k_multidot16_final<<<nv, 256, 0, s>>>(nv, kDot16Blocks, partial, out);
 }
 template <typename TV, typename TW>
 void launch_multi_axpy16(hipStream_t s, bool neg, int64_t n16, int nv, const TV* V,
                          const double* coef, TW* w) {
-    if (neg) k_multi_axpy16<TV, TW, true><<<nb_(n16, 256), 256, 0, s>>>(n16, nv, V, coef, w);
-    else k_multi_axpy16<TV, TW, false><<<nb_(n16, 256), 256, 0, s>>>(n16, nv, V, coef, w);
+    if (neg) k_multi_axpy16<TV, TW, true><<<nb_(n16 / 4, 256), 256, 0, s>>>(n16, nv, V, coef, w);
+    else k_multi_axpy16<TV, TW, false><<<nb_(n16 / 4, 256), 256, 0, s>>>(n16, nv, V, coef, w);
 }
 template <typename TO>
 void launch_scale16(hipStream_t s, int64_t n16, const double* w, const double* sc, TO* out) {

@@ -441,7 +441,8 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     for (auto& lv : h->L) CHK(setup_vectors(h, lv, h->mixed));
     const int64_t n0 = L0.len();
     CHK(h->alloc(&h->scal, 4096));
-    CHK(h->alloc(&h->part, (size_t)kDotBlocks * 72 * kNrhs));
+    CHK(h->alloc(&h->part, std::max((size_t)kDotBlocks * 72 * kNrhs,
+                                     (size_t)kDot16Blocks * kMaxBasis16 * kNrhs)));
     HIPCHK(hipHostMalloc((void**)&h->h_scal, 4096 * sizeof(double), hipHostMallocDefault));
     CHK(h->alloc(&h->r, n0));
     CHK(h->alloc(&h->z, n0));

@@ -64,6 +64,10 @@ void launch_convert(hipStream_t s, int64_t n, const Tin* in, Tout* out);
 
 // ---- vector kernels (k_blas.hip) -----------------------------------------
 constexpr int kDotBlocks = 512;
+// 16-column multi-dot: blocks of its partial pass and the largest number of
+// basis vectors (restart <= 64); the partial buffer holds both layouts
+constexpr int kDot16Blocks = 2048;
+constexpr int kMaxBasis16 = 64;
 void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial,
                 double* out);
 void launch_cg_update_xr(hipStream_t s, int64_t n, const double* scal, int i_rz, int i_pq,
