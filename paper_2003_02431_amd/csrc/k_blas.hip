@@ -112,16 +112,30 @@ __global__ __launch_bounds__(256) void k_multidot_partial(int64_t n, int nv,
                                                           const double* __restrict__ V,
                                                           const double* __restrict__ w,
                                                           double* __restrict__ partial) {
+    // groups of kG basis vectors share one pass over w; per-thread sums in
+    // ascending index order, then the fixed block reduction per vector
+    constexpr int kG = 8;
     __shared__ double sh[4];
-    for (int k = 0; k < nv; ++k) {
-        const double* v = V + (int64_t)k * n;
-        double acc = 0.0;
+    for (int k0 = 0; k0 < nv; k0 += kG) {
+        const int g = min(kG, nv - k0);
+        double acc[kG];
+#pragma unroll
+        for (int q = 0; q < kG; ++q) acc[q] = 0.0;
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * blockDim.x)
-            acc += v[i] * w[i];
-        const double t = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = t;
-        __syncthreads();
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const double wv = w[i];
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (q < g) acc[q] += V[(int64_t)(k0 + q) * n + i] * wv;
+        }
+#pragma unroll
+        for (int q = 0; q < kG; ++q) {
+            if (q < g) {                      // g is uniform: every thread takes the same path
+                const double t = block_sum(acc[q], sh);
+                if (threadIdx.x == 0) partial[(int64_t)(k0 + q) * gridDim.x + blockIdx.x] = t;
+                __syncthreads();
+            }
+        }
     }
 }
 

@@ -293,6 +293,158 @@ __global__ __launch_bounds__(256) void k_jacobi(int n_cells, int np_rt, const in
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small blocks (Np <= 8, the p1 and aggregation levels): a block row holds
+// only ~7 Np^2 entries, so with one wave per row the kernels are bound by
+// per-wave overhead.  Here a group of kGS = 16 lanes takes one block row
+// (SpMV) or one smoother cell (Jacobi), four groups per wave, with the same
+// column-chunk streaming and fixed reduction tree inside the group.  Row and
+// cell indices differ between the groups of a wave; every cross-lane read
+// stays inside the reading lane's own group.
+constexpr int kGS = 16;
+
+template <typename T, int NP>
+struct GrpCfg {
+    static constexpr int VEC = RowCfg<T, NP>::VEC;
+    static constexpr int L = NP / VEC;     // lanes per column
+    static constexpr int C = kGS / L;      // columns per load step of a group
+    static constexpr int CH = C * NP;
+};
+
+template <typename T, int NP>
+__device__ __forceinline__ void row_stream_g(int b0, int nb, const int* __restrict__ ci,
+                                             const T* __restrict__ A, const T* __restrict__ x,
+                                             int lane, T (&acc)[GrpCfg<T, NP>::VEC]) {
+    using R = GrpCfg<T, NP>;
+    constexpr int V = R::VEC;
+    const int gl = lane & (kGS - 1), gb = lane - gl;
+    const int q = gl % R::L, cl = gl / R::L;
+    const bool act = cl < R::C;
+    const int colreg = gl < nb ? ci[b0 + gl] : 0;
+    const T* Ar = A + (int64_t)b0 * (NP * NP);
+    const int E = nb * (NP * NP);
+    const int off = cl * NP + q * V;
+    for (int base = 0; base < E; base += R::CH) {
+        const int e = base + off;
+        const bool ok = act && e < E;
+        const int xi = e / NP;
+        const int bb = xi / NP;
+        int col = __shfl(colreg, gb + (bb & (kGS - 1)), 64);
+        if (ok) {
+            if (bb >= kGS) col = ci[b0 + bb];
+            const T xv = x[(int64_t)col * NP + (xi - bb * NP)];
+            T a[V];
+            load_vec<T, V>(Ar + e, a);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] += a[v] * xv;
+        }
+    }
+}
+
+// sum of the C column groups of a lane group into its lanes 0..L-1
+template <typename T, int V>
+__device__ __forceinline__ void reduce_groups_g(T (&acc)[V], int L, int C, int lane) {
+    const int gl = lane & (kGS - 1), gb = lane - gl;
+    const int cl = gl / L;
+    for (int s = 1; s < C; s <<= 1) {
+        const int src = min(lane + s * L, gb + kGS - 1);
+        const bool take = (cl % (2 * s) == 0) && (cl + s < C);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const T o = __shfl(acc[v], src, 64);
+            if (take) acc[v] += o;
+        }
+    }
+}
+
+template <typename T, int NP, int MODE>
+__global__ __launch_bounds__(256) void k_bsr_spmv_g(int n_rows, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci,
+                                                    const T* __restrict__ A,
+                                                    const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ y,
+                                                    int npc) {
+    using R = GrpCfg<T, NP>;
+    const int lane = threadIdx.x & 63;
+    const int row = (int)blockIdx.x * (256 / kGS) + (int)(threadIdx.x / kGS);
+    const bool valid = row < n_rows;
+    int beg = 0, nb = 0;
+    if (valid) {
+        beg = rp[row];
+        nb = rp[row + 1] - beg;
+    }
+    T acc[R::VEC];
+#pragma unroll
+    for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
+    row_stream_g<T, NP>(beg, nb, ci, A, x, lane, acc);
+    reduce_groups_g<T, R::VEC>(acc, R::L, R::C, lane);
+    const int gl = lane & (kGS - 1);
+    if (valid && gl < R::L) {
+#pragma unroll
+        for (int v = 0; v < R::VEC; ++v) {
+            const int r = gl * R::VEC + v;
+            const int64_t o = (int64_t)row * NP + r;
+            if (MODE == SPMV_AX) y[o] = acc[v];
+            else if (MODE == SPMV_RESID) y[o] = b[o] - acc[v];
+            else if (r < npc) y[(int64_t)row * npc + r] = b[o] - acc[v];
+        }
+    }
+}
+
+template <typename T, int NP, bool FIRST>
+__global__ __launch_bounds__(256) void k_jacobi_g(int n_cells, const int* __restrict__ cell_ptr,
+                                                  const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const T* __restrict__ A,
+                                                  const int64_t* __restrict__ doff,
+                                                  const T* __restrict__ D,
+                                                  const T* __restrict__ b,
+                                                  const T* __restrict__ xin,
+                                                  T* __restrict__ xout, T omega) {
+    using R = GrpCfg<T, NP>;
+    constexpr int G = 256 / kGS;
+    __shared__ T res[G][kMaxCell];
+    const int lane = threadIdx.x & 63;
+    const int grp = threadIdx.x / kGS, gl = lane & (kGS - 1);
+    const int cell = (int)blockIdx.x * G + grp;
+    const bool valid = cell < n_cells;
+    int r0 = 0, r1 = 0;
+    if (valid) {
+        r0 = cell_ptr[cell];
+        r1 = cell_ptr[cell + 1];
+    }
+    const int nc = (r1 - r0) * NP;                 // <= kMaxCell (checked on the host)
+    for (int row = r0; row < r1; ++row) {
+        T acc[R::VEC];
+#pragma unroll
+        for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
+        if (!FIRST) {
+            const int beg = rp[row], nb = rp[row + 1] - beg;
+            row_stream_g<T, NP>(beg, nb, ci, A, xin, lane, acc);
+            reduce_groups_g<T, R::VEC>(acc, R::L, R::C, lane);
+        }
+        if (gl < R::L) {
+#pragma unroll
+            for (int v = 0; v < R::VEC; ++v) {
+                const int r = gl * R::VEC + v;
+                res[grp][(row - r0) * NP + r] = b[(int64_t)row * NP + r] - acc[v];
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid) {
+        const T* Dc = D + doff[cell];
+        const int64_t base = (int64_t)r0 * NP;
+        for (int o = gl; o < nc; o += kGS) {
+            T a = 0;
+            for (int c = 0; c < nc; ++c) a += Dc[(int64_t)c * nc + o] * res[grp][c];
+            xout[base + o] = (FIRST ? T(0) : xin[base + o]) + omega * a;
+        }
+    }
+}
+
 template <typename T>
 __global__ void k_restrict_trunc(int n_rows, int npf, int npc, const T* __restrict__ rf,
                                  T* __restrict__ rc) {
@@ -396,10 +548,15 @@ template <typename T, int MODE>
 static void spmv_np(hipStream_t s, int n_rows, int np, const int* rp, const int* ci, const T* A,
                     const T* x, const T* b, T* y, int npc) {
     dim3 g(nblk(n_rows, 4)), blk(256);
+    dim3 gg(nblk(n_rows, 256 / kGS));
     switch (np) {
+#define XDG_NPG(N) \
+    case N: k_bsr_spmv_g<T, N, MODE><<<gg, blk, 0, s>>>(n_rows, rp, ci, A, x, b, y, npc); break;
+        XDG_NPG(1) XDG_NPG(3) XDG_NPG(4) XDG_NPG(6)
+#undef XDG_NPG
 #define XDG_NP(N) \
     case N: k_bsr_spmv<T, N, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc); break;
-        XDG_NP(1) XDG_NP(3) XDG_NP(4) XDG_NP(6) XDG_NP(10) XDG_NP(20) XDG_NP(35)
+        XDG_NP(10) XDG_NP(20) XDG_NP(35)
 #undef XDG_NP
         default: k_bsr_spmv<T, 0, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc);
     }
@@ -418,13 +575,21 @@ static void jacobi_np(hipStream_t s, int n_cells, int np, const int* cp, const i
                       const int* ci, const T* A, const int64_t* doff, const T* D, const T* b,
                       const T* xin, T* xout, T omega) {
     dim3 g(nblk(n_cells, 4)), blk(256);
+    dim3 gg(nblk(n_cells, 256 / kGS));
     switch (np) {
+#define XDG_NPG(N)                                                                          \
+    case N:                                                                                 \
+        k_jacobi_g<T, N, FIRST><<<gg, blk, 0, s>>>(n_cells, cp, rp, ci, A, doff, D, b, xin, \
+                                                    xout, omega);                           \
+        break;
+        XDG_NPG(1) XDG_NPG(3) XDG_NPG(4) XDG_NPG(6)
+#undef XDG_NPG
 #define XDG_NP(N)                                                                       \
     case N:                                                                             \
         k_jacobi<T, N, FIRST><<<g, blk, 0, s>>>(n_cells, np, cp, rp, ci, A, doff, D, b, \
                                                  xin, xout, omega);                     \
         break;
-        XDG_NP(1) XDG_NP(3) XDG_NP(4) XDG_NP(6) XDG_NP(10) XDG_NP(20) XDG_NP(35)
+        XDG_NP(10) XDG_NP(20) XDG_NP(35)
 #undef XDG_NP
         default:
             k_jacobi<T, 0, FIRST><<<g, blk, 0, s>>>(n_cells, np, cp, rp, ci, A, doff, D, b, xin,
