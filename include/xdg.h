@@ -124,7 +124,9 @@ int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
 /* Solves M^0 x = b.  x_dev holds the initial guess on entry and the solution
  * on return.  hist_host[k] = ||r_k||_2/||b||_2, k = 0..*iters (at most
  * hist_cap entries are written); *final_relres is the recomputed true FP64
- * residual.  Returns XDG_ENOCONV (x valid) when maxit is reached. */
+ * residual.  Returns XDG_ENOCONV (x valid) when maxit is reached.  b = 0
+ * (or a zero column of a 16-column b) gives x = 0 in that column whatever
+ * x held, with relative residual 0. */
 int xdg_solve(xdg_handle *h, const double *b_dev, double *x_dev, double *hist_host,
               int32_t hist_cap, int32_t *iters, double *final_relres);
 

@@ -606,4 +606,13 @@ template void launch_multi_axpy16<float, double>(hipStream_t, bool, int64_t, int
                                                  const double*, double*);
 template void launch_scale16<float>(hipStream_t, int64_t, const double*, const double*, float*);
 
+// x[e] = 0 where keep[e % 16] == 0 (in place)
+__global__ void k_zero_cols16(int64_t n16, const double* __restrict__ keep, double* x) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n16 && keep[e & 15] == 0.0) x[e] = 0.0;
+}
+void launch_zero_cols16(hipStream_t s, int64_t n16, const double* keep, double* x) {
+    k_zero_cols16<<<nb_(n16, 256), 256, 0, s>>>(n16, keep, x);
+}
+
 }  // namespace xdg

@@ -586,7 +586,9 @@ static int true_relres(xdg_handle* h, const double* b, const double* x, double* 
     launch_dot(h->s, f.len(), h->w, h->w, h->part, h->scal + S_RR);
     launch_dot(h->s, f.len(), b, b, h->part, h->scal + S_BB);
     CHK(read_scalars(h, S_BB, 2));
-    *out = std::sqrt(h->h_scal[S_RR]) / std::sqrt(h->h_scal[S_BB]);
+    // b = 0: the solution is 0 and the residual is reported as an absolute norm
+    const double nb = std::sqrt(h->h_scal[S_BB]);
+    *out = nb > 0.0 ? std::sqrt(h->h_scal[S_RR]) / nb : std::sqrt(h->h_scal[S_RR]);
     return XDG_OK;
 }
 

@@ -129,6 +129,7 @@ void launch_multi_axpy16(hipStream_t s, bool neg, int64_t n16, int nv, const TV*
                          const double* coef, TW* w);
 template <typename TO>
 void launch_scale16(hipStream_t s, int64_t n16, const double* w, const double* sc, TO* out);
+void launch_zero_cols16(hipStream_t s, int64_t n16, const double* keep, double* x);
 }  // namespace xdg
 
 namespace xdg {

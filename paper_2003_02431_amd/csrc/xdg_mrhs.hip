@@ -209,6 +209,16 @@ int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap,
     CHK(rd(h, M_BB, 16));
     double nb[kNrhs], beta[kNrhs], rel[kNrhs];
     for (int c = 0; c < kNrhs; ++c) nb[c] = std::sqrt(h->h_scal[M_BB + c]);
+    // a zero right-hand side column has the solution zero (whatever x0 held)
+    bool any_zero = false;
+    for (int c = 0; c < kNrhs; ++c) {
+        h->h_scal[M_SC + c] = nb[c] > 0.0 ? 1.0 : 0.0;
+        any_zero |= !(nb[c] > 0.0);
+    }
+    if (any_zero) {
+        CHK(wr(h, M_SC, 16));
+        launch_zero_cols16(s, n16, h->scal + M_SC, X);
+    }
     std::vector<double> H((size_t)kNrhs * (m + 1) * m), cs((size_t)kNrhs * m),
         sn((size_t)kNrhs * m), g((size_t)kNrhs * (m + 1));
     int jdone[kNrhs];
@@ -282,7 +292,8 @@ int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap,
                 else h->h_scal[M_SC + c] = 1.0 / hn;
             }
             for (int c = 0; c < kNrhs; ++c)
-                est = std::max(est, std::fabs(g[(size_t)c * (m + 1) + jdone[c]]) / nb[c]);
+                if (nb[c] > 0.0)
+                    est = std::max(est, std::fabs(g[(size_t)c * (m + 1) + jdone[c]]) / nb[c]);
             ++k;
             *iters = k;
             jmax = j + 1;

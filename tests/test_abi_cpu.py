@@ -48,6 +48,14 @@ def test_create_rejects_invalid_input(mutate, needle):
     assert needle in str(e.value)
 
 
+def test_create_rejects_empty_system():
+    from paper_2003_02431_amd import binding as B
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_create(np.array([0], np.int32), np.zeros(0, np.int32), np.zeros((0, 3, 3)),
+                     np.array([0], np.int32), [], B.options())
+    assert e.value.code == B.XDG_EINVAL
+
+
 def test_create_rejects_bad_options():
     from paper_2003_02431_amd import binding as B
     rp, ci, val, cp = _tiny()

@@ -47,6 +47,8 @@ def _case(name, torch):
             pr = problems.c4(seed=2, n=16, p=3, nrhs=K)
         elif name == "c4n16p2":
             pr = problems.c4(seed=3, n=16, p=2, nrhs=K)
+        elif name == "c4n8p4":
+            pr = problems.c4(seed=4, n=8, p=4, nrhs=K)
         else:
             pr = problems.c2(seed=3, n=8, hier=[("p", 1), ("h", 1)])
             pr.b = np.random.default_rng(9).uniform(-1, 1, (pr.n_rows * pr.np, K))
@@ -70,7 +72,7 @@ def _cols(v, L):
     return v.reshape(L, K)
 
 
-CASES = ["c2n8", "c4n16p2", "c4n16p3"]
+CASES = ["c2n8", "c4n16p2", "c4n16p3", "c4n8p4"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -191,3 +193,29 @@ def test_solve(name, torch):
          f"max err vs x*={worst_err:.2e}")
     assert rc == 0 and worst_res <= 1.05e-10 and worst_err <= 1e-8
     assert abs(fr - worst_res) <= 1e-2 * worst_res
+
+
+def test_zero_column_and_warm_start(torch):
+    """Degenerate input: one right-hand side column is zero (its solution is
+    zero, whatever the start held); the other columns start from a nonzero
+    guess and still reach error <= 1e-8."""
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case("c2n8", torch)
+    L = H.A[0].shape[0]
+    b = np.asarray(pr.b).reshape(L, K).copy()
+    b[:, 3] = 0.0
+    x0 = np.random.default_rng(31).uniform(-1, 1, (L, K))
+    x = S.vec(0, x0)
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0, b), x)
+    xg = _cols(x.cpu().numpy(), L)
+    assert rc == 0 and np.all(np.isfinite(hist))
+    assert np.all(xg[:, 3] == 0.0)
+    worst = 0.0
+    for c in range(K):
+        if c == 3:
+            continue
+        xs, _, _ = mg.pcg(H.A[0], b[:, c], H.vcycle, rtol=1e-13, maxit=2000)
+        worst = max(worst, _rel(xg[:, c], xs))
+    _log(f"  zero column + warm start: it={it} relres={fr:.2e} worst err={worst:.2e}")
+    assert worst <= 1e-8

@@ -43,6 +43,11 @@ def _make(name):
         return problems.c2(seed=3, n=8, hier=[("p", 1), ("h", 1)])
     if name == "c2n16":
         return problems.c2(seed=1, n=16)
+    if name == "c4n8p4":
+        # p = 4 (35 modes per block: the one-row-per-lane stream), ellipsoid
+        pr = problems.c4(seed=5, n=8, p=4, nrhs=1)
+        pr.b = np.asarray(pr.b).reshape(-1)
+        return pr
     raise KeyError(name)
 
 
@@ -61,7 +66,7 @@ def _case(name, torch):
     return _STATE[name]
 
 
-CASES = ["c1", "c2n8", "c2n16"]
+CASES = ["c1", "c2n8", "c2n16", "c4n8p4"]
 
 
 def _rel(a, b):
@@ -229,6 +234,21 @@ def test_mixed_flexible_cg(name, torch):
          f"err vs x*={err:.2e}")
     assert rc == 0 and tr <= 1.05 * rtol and abs(fr - tr) <= 1e-3 * tr
     assert err <= 1e-8
+    S.close()
+
+
+@pytest.mark.parametrize("krylov", ["cg", "fgmres"])
+def test_zero_rhs(krylov, torch):
+    """Degenerate input b = 0: the solution is zero whatever the start held,
+    with no iteration and a zero residual."""
+    from paper_2003_02431_amd import binding as B
+    pr, H, _ = _case("c2n8", torch)
+    K_ = B.XDG_CG if krylov == "cg" else B.XDG_FGMRES
+    S = B.Solver(pr, B.options(krylov=K_, rtol=1e-10))
+    x = S.vec(0, np.random.default_rng(2).uniform(-1, 1, H.A[0].shape[0]))
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0), x)
+    assert rc == 0 and it == 0 and fr == 0.0
+    assert float(torch.count_nonzero(x)) == 0
     S.close()
 
 
