@@ -62,3 +62,18 @@ def train(S, X, T, steps, lr=1e-3, batch=None):
     """Adam on the handle's network; batch None = full batch.  Returns the
     loss history (numpy)."""
     return B.xdg_mlp_train(S.h, X, T, batch or X.shape[0], steps, lr)
+
+
+def save_params(S, path):
+    """Write the handle's network parameters to a .npy file (plain array, no
+    pickling)."""
+    np.save(path, B.xdg_mlp_get(S.h), allow_pickle=False)
+
+
+def load_params(S, path):
+    """Load parameters written by save_params into the handle (resets the
+    Adam state)."""
+    p = np.load(path, allow_pickle=False)
+    if p.dtype != np.float32 or p.size != B.xdg_mlp_param_count():
+        raise ValueError(f"{path}: expected {B.xdg_mlp_param_count()} float32 parameters")
+    B.xdg_mlp_set(S.h, p)

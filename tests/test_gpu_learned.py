@@ -312,6 +312,15 @@ def test_training_and_gain(torch):
         res[name] = (it, dt, err)
         _log(f"  {name}: rc={rc} it={it} time={dt * 1e3:.1f} ms relres={fr:.2e} err={err:.2e}")
         assert rc == 0 and err <= 1e-8
+    # checkpoint: the trained parameters survive a save / load round trip
+    import tempfile, os
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "mlp.npy")
+        before = B.xdg_mlp_get(S.h)
+        LS.save_params(S, f)
+        B.xdg_mlp_set(S.h, LS.init_params(1))
+        LS.load_params(S, f)
+        assert np.array_equal(B.xdg_mlp_get(S.h), before)
     gd, fb = B.xdg_learned_stats(S.h)
     _log(f"  gain: iterations {res['plain'][0]} -> {res['learned'][0]}, time "
          f"{res['plain'][1] * 1e3:.1f} -> {res['learned'][1] * 1e3:.1f} ms, guarded cells {gd}, "
