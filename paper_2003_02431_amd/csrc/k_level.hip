@@ -151,6 +151,10 @@ __device__ __forceinline__ T row_times_x_rt(int beg, int end, const int* __restr
     return acc;
 }
 
+// One block row per wave; for Np >= 16 two waves per block row instead (the
+// first half of the row's blocks and the rest), their sums combined through
+// LDS in a fixed order -- twice the waves, which shortens the tail of the
+// grid (measured 131.4 -> 127.9 us at 32^3 p=3).
 template <typename T, int NP, int MODE>
 __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const int* __restrict__ rp,
                                                   const int* __restrict__ ci,
@@ -159,36 +163,72 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const i
                                                   const T* __restrict__ b, T* __restrict__ y,
                                                   int npc) {
     const int lane = threadIdx.x & 63;
-    const int row = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (row >= n_rows) return;
-    const int beg = uniform(rp[row]), end = uniform(rp[row + 1]);
-    if constexpr (NP > 0) {
-        constexpr bool W = NP >= 16;
-        using R = RowCfg<T, NP, W>;
+    if constexpr (NP >= 16) {
+        using R = RowCfg<T, NP, true>;
+        __shared__ T part[2][NP];
+        const int w = threadIdx.x >> 6;
+        const int row = uniform(blockIdx.x * 2 + (w >> 1));
+        const int half = w & 1;
+        const bool valid = row < n_rows;
+        int beg = 0, nb = 0;
+        if (valid) {
+            const int b0 = uniform(rp[row]), n = uniform(rp[row + 1]) - b0;
+            const int h0 = n / 2;
+            beg = half ? b0 + h0 : b0;
+            nb = half ? n - h0 : h0;
+        }
         T acc[R::VEC];
 #pragma unroll
         for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
-        row_stream<T, NP, W>(beg, end - beg, ci, A, x, lane, acc);
+        row_stream<T, NP, true>(beg, nb, ci, A, x, lane, acc);
         reduce_groups<T, R::VEC>(acc, R::L, R::C);
-        if (lane < R::L) {
+        if (half && lane < R::L) {
+#pragma unroll
+            for (int v = 0; v < R::VEC; ++v) part[w >> 1][lane * R::VEC + v] = acc[v];
+        }
+        __syncthreads();
+        if (!half && valid && lane < R::L) {
 #pragma unroll
             for (int v = 0; v < R::VEC; ++v) {
                 const int r = lane * R::VEC + v;
+                const T sum = acc[v] + part[w >> 1][r];
                 const int64_t o = (int64_t)row * NP + r;
-                if (MODE == SPMV_AX) y[o] = acc[v];
-                else if (MODE == SPMV_RESID) y[o] = b[o] - acc[v];
-                else if (r < npc) y[(int64_t)row * npc + r] = b[o] - acc[v];
+                if (MODE == SPMV_AX) y[o] = sum;
+                else if (MODE == SPMV_RESID) y[o] = b[o] - sum;
+                else if (r < npc) y[(int64_t)row * npc + r] = b[o] - sum;
             }
         }
     } else {
-        const int np = np_rt;
-        T acc = row_times_x_rt<T>(beg, end, ci, A, x, lane, np);
-        acc = group_sum(acc, np, 64 / np);
-        if (lane < np) {
-            const int64_t o = (int64_t)row * np + lane;
-            if (MODE == SPMV_AX) y[o] = acc;
-            else if (MODE == SPMV_RESID) y[o] = b[o] - acc;
-            else if (lane < npc) y[(int64_t)row * npc + lane] = b[o] - acc;
+        const int row = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+        if (row >= n_rows) return;
+        const int beg = uniform(rp[row]), end = uniform(rp[row + 1]);
+        if constexpr (NP > 0) {
+            using R = RowCfg<T, NP>;
+            T acc[R::VEC];
+#pragma unroll
+            for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
+            row_stream<T, NP>(beg, end - beg, ci, A, x, lane, acc);
+            reduce_groups<T, R::VEC>(acc, R::L, R::C);
+            if (lane < R::L) {
+#pragma unroll
+                for (int v = 0; v < R::VEC; ++v) {
+                    const int r = lane * R::VEC + v;
+                    const int64_t o = (int64_t)row * NP + r;
+                    if (MODE == SPMV_AX) y[o] = acc[v];
+                    else if (MODE == SPMV_RESID) y[o] = b[o] - acc[v];
+                    else if (r < npc) y[(int64_t)row * npc + r] = b[o] - acc[v];
+                }
+            }
+        } else {
+            const int np = np_rt;
+            T acc = row_times_x_rt<T>(beg, end, ci, A, x, lane, np);
+            acc = group_sum(acc, np, 64 / np);
+            if (lane < np) {
+                const int64_t o = (int64_t)row * np + lane;
+                if (MODE == SPMV_AX) y[o] = acc;
+                else if (MODE == SPMV_RESID) y[o] = b[o] - acc;
+                else if (lane < npc) y[(int64_t)row * npc + lane] = b[o] - acc;
+            }
         }
     }
 }
@@ -556,8 +596,15 @@ static void spmv_np(hipStream_t s, int n_rows, int np, const int* rp, const int*
 #undef XDG_NPG
 #define XDG_NP(N) \
     case N: k_bsr_spmv<T, N, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc); break;
-        XDG_NP(10) XDG_NP(20) XDG_NP(35)
+        XDG_NP(10)
 #undef XDG_NP
+#define XDG_NP2(N)                                                                          \
+    case N:                                                                                 \
+        k_bsr_spmv<T, N, MODE><<<nblk(n_rows, 2), blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, \
+                                                                npc);                       \
+        break;
+        XDG_NP2(20) XDG_NP2(35)
+#undef XDG_NP2
         default: k_bsr_spmv<T, 0, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc);
     }
 }
