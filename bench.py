@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the level-0 SpMV from the FETCH_SIZE / WRITE_SIZE
 # counter passes (scaled by a plain copy of known size), valid only for the
 # kernel source they were taken on.
-SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "eb0c04cd661c4368", "bytes": 771.2e6,
+SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "43f5b4274efc2df6", "bytes": 771.6e6,
                 "summary": "profiles/k_bsr_spmv_f64_np20_32cubed_hbm_counters.md"}
 
 
