@@ -45,7 +45,7 @@ enum {
 };
 
 enum { XDG_T_PTRUNC = 0, XDG_T_DENSE = 1 };
-enum { XDG_CG = 0, XDG_FGMRES = 1 };
+enum { XDG_CG = 0, XDG_FGMRES = 1, XDG_ORTHOMG = 2 };
 enum { XDG_FP64 = 0, XDG_MIXED = 1 };
 enum { XDG_JACOBI = 0, XDG_LEARNED = 1 };
 
@@ -84,6 +84,7 @@ typedef struct {
 
 typedef struct {
     int32_t krylov;           /* XDG_CG (flexible CG with XDG_MIXED) | XDG_FGMRES */
+                              /* | XDG_ORTHOMG (see xdg_solve)                  */
     int32_t restart;          /* FGMRES restart length (<= 64)                  */
     int32_t maxit;            /* Krylov iteration limit                         */
     int32_t nu_pre, nu_post;  /* block-Jacobi sweeps per level                  */
@@ -124,7 +125,14 @@ int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
 /* Solves M^0 x = b.  x_dev holds the initial guess on entry and the solution
  * on return.  hist_host[k] = ||r_k||_2/||b||_2, k = 0..*iters (at most
  * hist_cap entries are written); *final_relres is the recomputed true FP64
- * residual.  Returns XDG_ENOCONV (x valid) when maxit is reached.  b = 0
+ * residual.  Returns XDG_ENOCONV (x valid) when maxit is reached.
+ * krylov = XDG_ORTHOMG solves with the orthonormalisation multigrid of
+ * Section 3.3 (Algorithms ResMinimi and OrthoMG): residual minimisation over
+ * the directions of the pre-smoother, the coarse-grid correction (one such
+ * cycle on the level below, direct solve on the coarsest) and the
+ * post-smoother; the top level's family restarts once `restart` directions
+ * would be exceeded; hist_host[k] is the residual after k cycles; FP64 only.
+ * b = 0
  * (or a zero column of a 16-column b) gives x = 0 in that column whatever
  * x held, with relative residual 0. */
 int xdg_solve(xdg_handle *h, const double *b_dev, double *x_dev, double *hist_host,

@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxdg.so"
 XDG_OK, XDG_ENOCONV = 0, 1
 XDG_EINVAL, XDG_ENOMEM, XDG_EHIP, XDG_ENOTSPD, XDG_EBREAKDOWN = -1, -2, -3, -4, -5
 XDG_T_PTRUNC, XDG_T_DENSE = 0, 1
-XDG_CG, XDG_FGMRES = 0, 1
+XDG_CG, XDG_FGMRES, XDG_ORTHOMG = 0, 1, 2
 XDG_FP64, XDG_MIXED = 0, 1
 XDG_JACOBI, XDG_LEARNED = 0, 1
 

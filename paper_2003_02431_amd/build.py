@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libxdg.so")
 SOURCES = ["k_level.hip", "k_setup.hip", "k_blas.hip", "k_mrhs.hip", "k_mlp.hip",
-           "xdg_api.hip", "xdg_mrhs.hip", "xdg_mlp.hip"]
+           "xdg_api.hip", "xdg_mrhs.hip", "xdg_mlp.hip", "xdg_orthomg.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # no packed-FP32 instructions are generated (wrong results seen with them)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -96,6 +96,15 @@ void launch_fcg_update_p(hipStream_t s, int64_t n, const double* scal, int i_zq,
                          const double* z, double* p) {
     k_fcg_update_p<<<nblk(n, 256), 256, 0, s>>>(n, scal, i_zq, i_pq, z, p);
 }
+// scal[i] = sqrt(scal[i]); a zero (or negative) value becomes +inf so that a
+// division by it yields zero
+__global__ void k_sqrt_scalar(double* scal, int i) {
+    const double v = scal[i];
+    scal[i] = v > 0.0 ? sqrt(v) : __builtin_inf();
+}
+void launch_sqrt_scalar(hipStream_t s, double* scal, int i) {
+    k_sqrt_scalar<<<1, 1, 0, s>>>(scal, i);
+}
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
     k_axpy<<<nblk(n, 256), 256, 0, s>>>(n, a, x, y);
 }

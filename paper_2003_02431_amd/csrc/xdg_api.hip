@@ -219,6 +219,10 @@ static void smooth_from_zero(xdg_handle* h, Level& lv, int sweeps) {
     }
 }
 
+void xdg::smooth_from_zero_fp64(xdg_handle* h, Level& lv, int sweeps) {
+    smooth_from_zero<double>(h, lv, sweeps);
+}
+
 template <typename T>
 static void smooth_more(xdg_handle* h, Level& lv, int sweeps) {
     T* b = P<T>::b(lv);
@@ -323,12 +327,17 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
         return fail(XDG_EINVAL, "xdg_create: non-finite matrix entry");
     if (!(opt->omega > 0.0 && opt->omega < 2.0) || opt->nu_pre < 0 || opt->nu_post < 0 ||
         opt->maxit < 1 || !(opt->rtol > 0.0) || (opt->nrhs != 1 && opt->nrhs != kNrhs) ||
-        (opt->krylov != XDG_CG && opt->krylov != XDG_FGMRES) ||
+        (opt->krylov != XDG_CG && opt->krylov != XDG_FGMRES && opt->krylov != XDG_ORTHOMG) ||
         (opt->precision != XDG_FP64 && opt->precision != XDG_MIXED))
         return fail(XDG_EINVAL, "xdg_create: invalid options");
     CHK(xdg::learned_validate(opt, A0->np));
     if (opt->krylov == XDG_FGMRES && (opt->restart < 1 || opt->restart > 64))
         return fail(XDG_EINVAL, "xdg_create: FGMRES restart must be in [1, 64]");
+    if (opt->krylov == XDG_ORTHOMG &&
+        (opt->restart < 3 || opt->restart > 64 || opt->precision != XDG_FP64 ||
+         opt->nrhs != 1 || opt->smoother != XDG_JACOBI))
+        return fail(XDG_EINVAL, "xdg_create: the orthonormalisation multigrid needs restart in "
+                                "[3, 64], XDG_FP64, nrhs = 1 and block Jacobi");
     if (opt->krylov == XDG_CG && opt->nu_pre != opt->nu_post)
         return fail(XDG_EINVAL, "xdg_create: CG needs nu_pre == nu_post (symmetric V-cycle)");
     if (opt->nrhs == kNrhs) CHK(mrhs_validate(opt, A0->np, T, n_levels));
@@ -454,6 +463,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
         CHK(h->alloc(&h->Z, (size_t)opt->restart * n0));
     }
     if (h->nrhs == kNrhs) CHK(mrhs_allocate(h));
+    if (opt->krylov == XDG_ORTHOMG) CHK(xdg::orthomg_allocate(h));
 
     // -- numeric phase ------------------------------------------------------
     {
@@ -765,8 +775,9 @@ extern "C" int xdg_solve(xdg_handle* h, const double* b, double* x, double* hist
         if (rcm == XDG_ENOCONV) fail(0, "xdg_solve: iteration limit reached");
         return rcm;
     }
-    int rc = h->opt.krylov == XDG_CG ? solve_cg(h, b, x, hist, hist_cap, &it)
-                                     : solve_fgmres(h, b, x, hist, hist_cap, &it);
+    int rc = h->opt.krylov == XDG_CG       ? solve_cg(h, b, x, hist, hist_cap, &it)
+             : h->opt.krylov == XDG_FGMRES ? solve_fgmres(h, b, x, hist, hist_cap, &it)
+                                           : xdg::solve_orthomg(h, b, x, hist, hist_cap, &it);
     *iters = it;
     if (rc < 0) return rc;
     CHK(true_relres(h, b, x, final_relres));

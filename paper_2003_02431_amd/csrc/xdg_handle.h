@@ -116,6 +116,10 @@ struct xdg_handle {
     int* row_species = nullptr;
     float* cell_geom = nullptr;
     int* d_nguard = nullptr;
+    // orthonormalisation multigrid: per level the family Z, W = M Z, the
+    // iterate, its residual, a work vector, and the family size
+    std::vector<double*> omZ, omW, omX, omR, omT;
+    std::vector<int> om_count;
     float guard = 4.0f;             // |proposal| / |Jacobi step| above this: plain step
     bool learned_ready = false;     // weights and features present
     bool learned_off = false;       // solver-level fallback taken in this solve
@@ -153,6 +157,13 @@ int mrhs_smooth(xdg_handle* h, int level, const double* B, double* X, int sweeps
 int mrhs_vcycle(xdg_handle* h, const double* R, double* Z);
 int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap, int* iters,
                double* final_relres);
+}  // namespace xdg
+
+namespace xdg {
+// orthonormalisation multigrid (xdg_orthomg.hip) and the FP64 smoother it uses
+int orthomg_allocate(xdg_handle* h);
+int solve_orthomg(xdg_handle* h, const double* b, double* x, double* hist, int cap, int* iters);
+void smooth_from_zero_fp64(xdg_handle* h, Level& lv, int sweeps);
 }  // namespace xdg
 
 namespace xdg {

@@ -94,6 +94,7 @@ void launch_multi_axpy(hipStream_t s, int64_t n, int nv, const double* V, const 
 // y = x / scal[i]
 void launch_div_scalar(hipStream_t s, int64_t n, const double* scal, int i, const double* x,
                        double* y);
+void launch_sqrt_scalar(hipStream_t s, double* scal, int i);
 }  // namespace xdg
 
 namespace xdg {

@@ -61,7 +61,9 @@ def test_create_rejects_bad_options():
     rp, ci, val, cp = _tiny()
     for opt in (B.options(omega=2.5), B.options(precision=7),
                 B.options(krylov=B.XDG_FGMRES, restart=0), B.options(nu_pre=2, nu_post=1),
-                B.options(rtol=0.0), B.options(nrhs=2)):
+                B.options(rtol=0.0), B.options(nrhs=2),
+                B.options(krylov=B.XDG_ORTHOMG, restart=2),
+                B.options(krylov=B.XDG_ORTHOMG, precision=B.XDG_MIXED), B.options(krylov=5)):
         with pytest.raises(B.XdgError) as e:
             B.xdg_create(rp, ci, val, cp, [], opt)
         assert e.value.code == B.XDG_EINVAL

@@ -252,6 +252,55 @@ def test_zero_rhs(krylov, torch):
     S.close()
 
 
+@pytest.mark.parametrize("name", ["c1", "c2n8", "c4n8p4"])
+def test_orthomg_one_cycle(name, torch):
+    """One cycle of the orthonormalisation multigrid from x = 0 against the
+    oracle's cycle (Gauss-Jordan vs Cholesky coarse inverses: the kappa bound
+    of the V-cycle test)."""
+    from oracle import orthomg
+    from paper_2003_02431_amd import binding as B
+    pr, H, _ = _case(name, torch)
+    b = np.asarray(pr.b).reshape(-1)
+    S = B.Solver(pr, B.options(krylov=B.XDG_ORTHOMG, restart=12, maxit=1, rtol=1e-30))
+    x = S.vec(0)
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0, b), x)
+    xr, hr, kr = orthomg.solve(H, b, rtol=1e-30, max_cycles=1, restart=12)
+    kappa = np.linalg.cond(H.A[-1].toarray())
+    e = _rel(x.cpu().numpy(), xr)
+    _log(f"  {name}: one OrthoMG cycle rel diff {e:.2e}, relres gpu {hist[-1]:.3e} oracle "
+         f"{hr[-1]:.3e}")
+    assert rc == B.XDG_ENOCONV and it == 1 and kr == 1
+    assert e <= 10 * _kappa_tol(kappa)
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2n8", "c2n16"])
+def test_orthomg_solve(name, torch):
+    """The orthonormalisation-multigrid solver to rel.res 1e-10 (restart 12):
+    cycle count within 1 of the oracle's, residual histories alike, error
+    against the oracle's x* <= 1e-8."""
+    from oracle import mg, orthomg
+    from paper_2003_02431_amd import binding as B
+    pr, H, _ = _case(name, torch)
+    b = np.asarray(pr.b).reshape(-1)
+    S = B.Solver(pr, B.options(krylov=B.XDG_ORTHOMG, restart=12, maxit=400, rtol=1e-10))
+    x = S.vec(0)
+    rc, it, fr, hist = B.xdg_solve(S.h, S.vec(0, b), x)
+    xr, hr, kr = orthomg.solve(H, b, rtol=1e-10, max_cycles=400, restart=12)
+    xs, _, _ = mg.pcg(H.A[0], b, H.vcycle, rtol=1e-13, maxit=2000)
+    xg = x.cpu().numpy()
+    tr = np.linalg.norm(b - H.A[0] @ xg) / np.linalg.norm(b)
+    m = min(len(hist), len(hr))
+    hd = float(np.max(np.abs(np.log10(hist[:m]) - np.log10(hr[:m]))))
+    err = _rel(xg, xs)
+    _log(f"  {name}: OrthoMG gpu cycles={it} oracle={kr} relres={tr:.2e} "
+         f"max |log10 hist diff|={hd:.2e} err vs x*={err:.2e}")
+    assert rc == 0 and abs(it - kr) <= 1 and tr <= 1.05e-10
+    assert hd <= 0.05 and err <= 1e-8
+    assert all(h1 <= h0 * (1 + 1e-10) for h0, h1 in zip(hist, hist[1:]))
+    S.close()
+
+
 def test_mixed_vcycle_is_fp32(torch):
     """The mixed handle's V-cycle runs in FP32: it differs from the FP64 cycle
     by FP32 rounding, not by zero and not by more."""
