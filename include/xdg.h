@@ -134,7 +134,8 @@ int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
  * would be exceeded; hist_host[k] is the residual after k cycles; FP64 only.
  * b = 0
  * (or a zero column of a 16-column b) gives x = 0 in that column whatever
- * x held, with relative residual 0. */
+ * x held, with relative residual 0.  A non-finite b or initial residual
+ * returns XDG_EINVAL before any iteration. */
 int xdg_solve(xdg_handle *h, const double *b_dev, double *x_dev, double *hist_host,
               int32_t hist_cap, int32_t *iters, double *final_relres);
 

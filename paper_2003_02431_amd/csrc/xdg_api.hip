@@ -618,6 +618,9 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
     launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
     CHK(read_scalars(h, S_BB, 2));
     const double nb = std::sqrt(h->h_scal[S_BB]);
+    if (!std::isfinite(nb)) return fail(XDG_EINVAL, "xdg_solve: non-finite right-hand side");
+    if (!std::isfinite(h->h_scal[S_RR]))
+        return fail(XDG_EINVAL, "xdg_solve: non-finite initial guess");
     if (nb == 0.0) {
         HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
         *iters = 0;
@@ -672,6 +675,7 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
     launch_dot(s, n, b, b, h->part, h->scal + S_BB);
     CHK(read_scalars(h, S_BB, 1));
     const double nb = std::sqrt(h->h_scal[S_BB]);
+    if (!std::isfinite(nb)) return fail(XDG_EINVAL, "xdg_solve: non-finite right-hand side");
     *iters = 0;
     if (nb == 0.0) {
         HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
@@ -688,6 +692,7 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
         launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
         CHK(read_scalars(h, S_RR, 1));
         const double beta = std::sqrt(h->h_scal[S_RR]);
+        if (!std::isfinite(beta)) return fail(XDG_EINVAL, "xdg_solve: non-finite residual");
         const double rel = beta / nb;
         if (k < cap) hist[k] = rel;       // replaces the estimate of the last inner step
         if (rel <= h->opt.rtol) return XDG_OK;

@@ -199,6 +199,8 @@ int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap,
         double mx = 0.0;
         for (int c = 0; c < kNrhs; ++c) {
             beta_out[c] = std::sqrt(h->h_scal[M_RR + c]);
+            if (!std::isfinite(beta_out[c]))
+                return fail(XDG_EINVAL, "xdg_solve: non-finite residual");
             rel_out[c] = nb[c] > 0.0 ? beta_out[c] / nb[c] : 0.0;
             mx = std::max(mx, rel_out[c]);
         }
@@ -208,7 +210,10 @@ int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap,
     launch_multidot16<double>(s, n16, 1, B, B, h->part, h->scal + M_BB);
     CHK(rd(h, M_BB, 16));
     double nb[kNrhs], beta[kNrhs], rel[kNrhs];
-    for (int c = 0; c < kNrhs; ++c) nb[c] = std::sqrt(h->h_scal[M_BB + c]);
+    for (int c = 0; c < kNrhs; ++c) {
+        nb[c] = std::sqrt(h->h_scal[M_BB + c]);
+        if (!std::isfinite(nb[c])) return fail(XDG_EINVAL, "xdg_solve: non-finite right-hand side");
+    }
     // a zero right-hand side column has the solution zero (whatever x0 held)
     bool any_zero = false;
     for (int c = 0; c < kNrhs; ++c) {

@@ -135,6 +135,7 @@ int solve_orthomg(xdg_handle* h, const double* b, double* x, double* hist, int c
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const double nb = std::sqrt(h->h_scal[O_RR]);
+    if (!std::isfinite(nb)) return fail(XDG_EINVAL, "xdg_solve: non-finite right-hand side");
     if (nb == 0.0) {
         HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
         if (cap > 0) hist[0] = 0.0;
@@ -146,8 +147,12 @@ int solve_orthomg(xdg_handle* h, const double* b, double* x, double* hist, int c
         if (cap > 1) hist[1] = 0.0;
         return XDG_OK;
     }
-    // the top level works on the caller's x
-    double* xs = h->omX[0];
+    // the top level works on the caller's x (restored on every return path)
+    struct Restore {
+        xdg_handle* h;
+        double* p;
+        ~Restore() { h->omX[0] = p; }
+    } restore{h, h->omX[0]};
     h->omX[0] = x;
     int rc = XDG_ENOCONV;
     launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->omR[0], 0);
@@ -159,6 +164,7 @@ int solve_orthomg(xdg_handle* h, const double* b, double* x, double* hist, int c
         HIPCHK(hipStreamSynchronize(s));
         HIPCHK(hipGetLastError());
         const double rel = std::sqrt(h->h_scal[O_RR]) / nb;
+        if (!std::isfinite(rel)) return fail(XDG_EINVAL, "xdg_solve: non-finite residual");
         if (k < cap) hist[k] = rel;
         *iters = k;
         if (rel <= h->opt.rtol) {
@@ -167,13 +173,8 @@ int solve_orthomg(xdg_handle* h, const double* b, double* x, double* hist, int c
         }
         if (k >= h->opt.maxit) break;
         if (h->om_count[0] + 3 > h->opt.restart) h->om_count[0] = 0;   // restart: x0 := x
-        const int e = om_cycle(h, 0);
-        if (e < 0) {
-            h->omX[0] = xs;
-            return e;
-        }
+        CHK(om_cycle(h, 0));
     }
-    h->omX[0] = xs;
     return rc;
 }
 

@@ -219,3 +219,14 @@ def test_zero_column_and_warm_start(torch):
         worst = max(worst, _rel(xg[:, c], xs))
     _log(f"  zero column + warm start: it={it} relres={fr:.2e} worst err={worst:.2e}")
     assert worst <= 1e-8
+
+
+def test_non_finite_column_is_rejected(torch):
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case("c2n8", torch)
+    L = H.A[0].shape[0]
+    b = np.asarray(pr.b).reshape(L, K).copy()
+    b[11, 5] = np.nan
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_solve(S.h, S.vec(0, b), S.vec(0))
+    assert e.value.code == B.XDG_EINVAL

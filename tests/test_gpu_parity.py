@@ -301,6 +301,32 @@ def test_orthomg_solve(name, torch):
     S.close()
 
 
+@pytest.mark.parametrize("krylov", ["cg", "fgmres", "orthomg"])
+def test_non_finite_input_is_rejected(krylov, torch):
+    """A NaN in b or in the initial guess returns XDG_EINVAL before any
+    iteration (no NaN propagates into a 'converged' answer)."""
+    from paper_2003_02431_amd import binding as B
+    pr, H, _ = _case("c2n8", torch)
+    K_ = {"cg": B.XDG_CG, "fgmres": B.XDG_FGMRES, "orthomg": B.XDG_ORTHOMG}[krylov]
+    S = B.Solver(pr, B.options(krylov=K_, restart=12, rtol=1e-10))
+    b = np.asarray(pr.b, dtype=np.float64).reshape(-1).copy()
+    bad = b.copy()
+    bad[5] = np.nan
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_solve(S.h, S.vec(0, bad), S.vec(0))
+    assert e.value.code == B.XDG_EINVAL
+    x0 = np.zeros_like(b)
+    x0[7] = np.inf
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_solve(S.h, S.vec(0, b), S.vec(0, x0))
+    assert e.value.code == B.XDG_EINVAL
+    # the handle still solves afterwards
+    x = S.vec(0)
+    rc, it, fr, _ = B.xdg_solve(S.h, S.vec(0, b), x)
+    assert rc == 0 and fr <= 1.05e-10
+    S.close()
+
+
 def test_mixed_vcycle_is_fp32(torch):
     """The mixed handle's V-cycle runs in FP32: it differs from the FP64 cycle
     by FP32 rounding, not by zero and not by more."""
