@@ -51,11 +51,12 @@ def features(H, row_species, cell_geom, r):
     return F, j, s
 
 
-def first_sweep(H, row_species, cell_geom, theta, r, guard):
+def first_sweep(H, row_species, cell_geom, theta, r, guard, bf16=False):
     """x after the learned first sweep from x = 0; also the number of cells
-    that kept the plain Jacobi step."""
+    that kept the plain Jacobi step.  bf16: the network runs with bfloat16
+    operands (mlp.forward_bf16)."""
     F, j, s = features(H, row_species, cell_geom, r)
-    Y, _ = mlp.forward(theta, F)
+    Y = mlp.forward_bf16(theta, F) if bf16 else mlp.forward(theta, F)[0]
     bad = ~np.all(np.isfinite(Y), axis=1) | ~(np.linalg.norm(Y, axis=1) <= guard)
     Y[bad] = 0.0
     cp = H.cell_ptr[0]
@@ -87,7 +88,7 @@ def pairs(H, row_species, cell_geom, b, xk, xs, clip=0.0):
     return F, T
 
 
-def vcycle(H, row_species, cell_geom, theta, r, guard, level=0):
+def vcycle(H, row_species, cell_geom, theta, r, guard, level=0, bf16=False):
     """The V-cycle of oracle.mg.Hierarchy.vcycle with the learned first sweep
     on level 0 (the remaining nu_pre - 1 sweeps and the post-smoothing are
     plain damped block Jacobi)."""
@@ -95,7 +96,7 @@ def vcycle(H, row_species, cell_geom, theta, r, guard, level=0):
         return H.vcycle(r, level)
     from .mg import jacobi
     A, D = H.A[0], H.Dinv[0]
-    x, _ = first_sweep(H, row_species, cell_geom, theta, r, guard)
+    x, _ = first_sweep(H, row_species, cell_geom, theta, r, guard, bf16)
     x = jacobi(A, D, r, x, H.omega, H.nu_pre - 1)
     rc = H.R[0].T @ (r - A @ x)
     x = x + H.R[0] @ H.vcycle(rc, 1)

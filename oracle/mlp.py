@@ -43,6 +43,26 @@ def forward(theta, X):
     return Y, (Z1, H1, Z2, H2)
 
 
+def bf16(a):
+    """Round to the nearest bfloat16 value (ties to even), returned as float64:
+    keep the upper 16 bits of the IEEE single-precision pattern after adding
+    0x7fff plus the lowest kept bit."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta, X):
+    """The network with bfloat16 operands: inputs, weights and the two hidden
+    activations rounded to bf16, biases and accumulation in (at least) FP32.
+    Returns Y [n, 40]."""
+    W1, b1, W2, b2, W3, b3 = unpack(theta)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    H1 = bf16(gelu(bf16(X) @ bf16(W1).T + f32(b1)))
+    H2 = bf16(gelu(H1 @ bf16(W2).T + f32(b2)))
+    return H2 @ bf16(W3).T + f32(b3)
+
+
 def loss(theta, X, T):
     Y, _ = forward(theta, X)
     return float(np.sum((Y - T) ** 2) / X.shape[0])

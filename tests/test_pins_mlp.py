@@ -54,3 +54,29 @@ def test_adam_first_step_is_signed_lr():
     th, m, v = mlp.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
     assert np.allclose(th[:3], -0.01 * np.sign(g[:3]), rtol=1e-5)
     assert th[3] == 0.0
+
+
+def test_bf16_rounding_values():
+    """Round-to-nearest-even onto the bfloat16 grid (8 significand bits):
+    exact grid values stay, halfway cases go to the even neighbour."""
+    b = mlp.bf16
+    assert b(1.0) == 1.0 and b(-2.5) == -2.5 and b(0.0) == 0.0
+    u = 2.0 ** -7                                   # bf16 spacing just above 1
+    assert b(1.0 + u / 2) == 1.0                    # tie -> even (1.0)
+    assert b(1.0 + 3 * u / 2) == 1.0 + 2 * u        # tie -> even (1 + 2u)
+    assert b(1.0 + 0.6 * u) == 1.0 + u
+    assert b(2.0 - 2.0 ** -9) == 2.0                # rounds up across the binade
+    x = np.random.default_rng(0).standard_normal(1000)
+    assert np.all(np.abs(b(x) - x) <= np.abs(x) * 2.0 ** -8 * (1 + 1e-12))
+
+
+def test_bf16_forward_close_to_fp64():
+    """The bf16 network differs from the FP64 one by rounding only: a few
+    bf16 units relative to the output scale."""
+    rng = np.random.default_rng(3)
+    theta = mlp.init_params(rng) + 0.05 * rng.standard_normal(mlp.N_PARAM)
+    X = rng.standard_normal((50, mlp.N_IN))
+    Y, _ = mlp.forward(theta, X)
+    Yb = mlp.forward_bf16(theta, X)
+    e = np.max(np.abs(Yb - Y)) / np.max(np.abs(Y))
+    assert 1e-4 < e < 5e-2
