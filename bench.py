@@ -288,7 +288,8 @@ def bench_learned(args):
     b = S.vec(0, pr.b)
     xs = tight(S, b)
     res = {}
-    for name, sm in (("plain", B.XDG_JACOBI), ("learned", B.XDG_LEARNED)):
+    for name, sm in (("plain", B.XDG_JACOBI), ("learned", B.XDG_LEARNED),
+                     ("learned_bf16", B.XDG_LEARNED_BF16)):
         S.set_smoother(sm)
         x = S.vec(0)
         B.xdg_solve(S.h, b, x, hist_cap=3000)     # warm-up
@@ -315,10 +316,12 @@ def bench_learned(args):
                       "block_rows": int(pr.n_rows), "nnzb": int(pr.col_idx.size),
                       "train_pairs": int(X.shape[0]), "clip": clip, "guard": guard,
                       "krylov": "FGMRES(30)", "rtol": opt["rtol"]},
-           "plain": res["plain"], "learned": res["learned"],
+           "plain": res["plain"], "learned": res["learned"], "learned_bf16": res["learned_bf16"],
            "iteration_gain": res["plain"]["iters"] - res["learned"]["iters"],
            "time_ratio_learned_over_plain": round(res["learned"]["time_s"] /
                                                   res["plain"]["time_s"], 3),
+           "time_ratio_bf16_over_fp32_network": round(res["learned_bf16"]["time_s"] /
+                                                      res["learned"]["time_s"], 3),
            "pairs_s": round(t_pairs, 3), "train_s": round(t_train, 3),
            "train_loss": [float(hist[0]), float(hist[-1])],
            "guarded_cells": gd, "solver_fallbacks": fb}

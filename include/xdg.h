@@ -47,7 +47,7 @@ enum {
 enum { XDG_T_PTRUNC = 0, XDG_T_DENSE = 1 };
 enum { XDG_CG = 0, XDG_FGMRES = 1, XDG_ORTHOMG = 2 };
 enum { XDG_FP64 = 0, XDG_MIXED = 1 };
-enum { XDG_JACOBI = 0, XDG_LEARNED = 1 };
+enum { XDG_JACOBI = 0, XDG_LEARNED = 1, XDG_LEARNED_BF16 = 2 };
 
 typedef struct xdg_handle xdg_handle;
 
@@ -89,7 +89,7 @@ typedef struct {
     int32_t maxit;            /* Krylov iteration limit                         */
     int32_t nu_pre, nu_post;  /* block-Jacobi sweeps per level                  */
     int32_t precision;        /* XDG_FP64 | XDG_MIXED (FP32 V-cycle)            */
-    int32_t smoother;         /* XDG_JACOBI | XDG_LEARNED (see below)           */
+    int32_t smoother;         /* XDG_JACOBI | XDG_LEARNED | XDG_LEARNED_BF16    */
     int32_t nrhs;             /* 1, or 16 (needs XDG_FGMRES + XDG_MIXED): block */
                               /* products of the V-cycle on FP32 MFMA, Arnoldi  */
                               /* matvec and restart residuals on FP64 MFMA      */
@@ -194,6 +194,10 @@ int xdg_setup_time(xdg_handle *h, double *ms);
  * residual estimate by less than a factor 0.99 while the network is active
  * switches the network off for the rest of that solve (flexible GMRES
  * accepts the changed preconditioner).
+ * XDG_LEARNED_BF16 runs the same network on bf16 matrix cores: features,
+ * weights and both hidden activations rounded to bfloat16 (nearest even),
+ * products accumulated and biases added in FP32, 16 cells per MFMA tile;
+ * the weights are repacked after every xdg_mlp_set / xdg_mlp_train.
  * Parameters: 9704 FP32 values, weights row-major [out][in]:
  *   W1[64][45] b1[64] W2[64][64] b2[64] W3[40][64] b3[40]. */
 int32_t xdg_mlp_param_count(void);

@@ -18,7 +18,7 @@ XDG_EINVAL, XDG_ENOMEM, XDG_EHIP, XDG_ENOTSPD, XDG_EBREAKDOWN = -1, -2, -3, -4, 
 XDG_T_PTRUNC, XDG_T_DENSE = 0, 1
 XDG_CG, XDG_FGMRES, XDG_ORTHOMG = 0, 1, 2
 XDG_FP64, XDG_MIXED = 0, 1
-XDG_JACOBI, XDG_LEARNED = 0, 1
+XDG_JACOBI, XDG_LEARNED, XDG_LEARNED_BF16 = 0, 1, 2
 
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)

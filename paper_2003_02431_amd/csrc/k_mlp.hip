@@ -399,6 +399,244 @@ __global__ __launch_bounds__(256) void k_learned_correct(int n_cells, const int*
 }
 
 // ---------------------------------------------------------------------------
+// BF16 inference: 16 cells per wave through the three layers as
+// v_mfma_f32_16x16x16_bf16 products (bf16 operands, FP32 accumulation).
+// Lane layouts (checked on gfx950): A lane l holds A[l % 16][4 (l / 16) + i],
+// B lane l holds B[4 (l / 16) + i][l % 16], D lane l holds
+// D[4 (l / 16) + r][l % 16], i, r < 4.  Rows are cells; the weights are the
+// B operands, packed once per parameter change: tile (t, q) of layer L holds
+// W_L[16 t + n][16 q + k] at B[k][n] (zero outside the matrix; the 45 inputs
+// are padded to 48, the 40 outputs to 48).
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kT1 = 4, kQ1 = 3, kT2 = 4, kQ2 = 4, kT3 = 3, kQ3 = 4;
+constexpr int kTiles = kT1 * kQ1 + kT2 * kQ2 + kT3 * kQ3;   // 40 operand tiles
+constexpr int kPackedBf16 = kTiles * 64 * 4;
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+    // round to nearest even (finite inputs; NaN stays NaN through the guard)
+    const unsigned u = __float_as_uint(f);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void k_pack_bf16(const float* __restrict__ P, unsigned short* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kPackedBf16) return;
+    const int i = e & 3, l = (e >> 2) & 63, tile = e >> 8;
+    const int n = l & 15, k = 4 * (l >> 4) + i;
+    float v = 0.f;
+    if (tile < kT1 * kQ1) {
+        const int t = tile / kQ1, q = tile % kQ1, row = 16 * t + n, col = 16 * q + k;
+        if (col < kIn) v = P[oW1 + row * kIn + col];
+    } else if (tile < kT1 * kQ1 + kT2 * kQ2) {
+        const int tt = tile - kT1 * kQ1, t = tt / kQ2, q = tt % kQ2;
+        v = P[oW2 + (16 * t + n) * kHid + 16 * q + k];
+    } else {
+        const int tt = tile - kT1 * kQ1 - kT2 * kQ2, t = tt / kQ3, q = tt % kQ3;
+        const int row = 16 * t + n;
+        if (row < kOut) v = P[oW3 + row * kHid + 16 * q + k];
+    }
+    out[e] = to_bf16(v);
+}
+
+constexpr int kBatch = 16;                 // cells per wave and batch (MFMA rows)
+constexpr int kBatchRows = 2 * kBatch;
+
+__global__ __launch_bounds__(256) void k_learned_correct_bf16(
+    int n_cells, const int* __restrict__ cell_ptr, const int* __restrict__ row_species,
+    const float* __restrict__ geom, const unsigned short* __restrict__ wpk,
+    const float* __restrict__ params, float guard, double* __restrict__ x,
+    int* __restrict__ nguard) {
+    constexpr int NP = 20;
+    __shared__ double xs[4][kBatchRows * NP];
+    __shared__ double scs[4][kBatch];
+    __shared__ __align__(16) unsigned short fa[4][kBatch][48];          // features (A operand of layer 1)
+    __shared__ __align__(16) unsigned short ha[4][kBatch][kHid];        // hidden layer 1
+    __shared__ __align__(16) unsigned short hb[4][kBatch][kHid];        // hidden layer 2
+    __shared__ float ya[4][kBatch][48];                    // outputs
+    __shared__ float gs[4][kBatch * 5];
+    __shared__ int badc[4][kBatch];
+    __shared__ int spc[4][kBatchRows];
+    __shared__ int cps[4][kBatch + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // weight operands and biases in registers
+    bf16x4 B1[kT1 * kQ1], B2[kT2 * kQ2], B3[kT3 * kQ3];
+    const bf16x4* W = reinterpret_cast<const bf16x4*>(wpk);
+#pragma unroll
+    for (int t = 0; t < kT1 * kQ1; ++t) B1[t] = W[t * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < kT2 * kQ2; ++t) B2[t] = W[(kT1 * kQ1 + t) * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < kT3 * kQ3; ++t) B3[t] = W[(kT1 * kQ1 + kT2 * kQ2 + t) * 64 + lane];
+    float bb1[kT1], bb2[kT2], bb3[kT3];
+#pragma unroll
+    for (int t = 0; t < kT1; ++t) bb1[t] = params[oB1 + 16 * t + li];
+#pragma unroll
+    for (int t = 0; t < kT2; ++t) bb2[t] = params[oB2 + 16 * t + li];
+#pragma unroll
+    for (int t = 0; t < kT3; ++t) bb3[t] = 16 * t + li < kOut ? params[oB3 + 16 * t + li] : 0.f;
+    int guarded = 0;
+    const int n_batches = (n_cells + kBatch - 1) / kBatch;
+    constexpr int kXv = kBatchRows * NP / 64;      // x values per lane and batch
+    // next batch, loaded while the current one runs: cell pointers and
+    // geometry first, then (once the pointers are in) x and the species
+    int cp_n = 0;
+    float g_n0 = 0.f, g_n1 = 0.f;
+    double xv[kXv];
+    int sp_n = 0;
+    auto fetch_cells = [&](int b) {
+        if (b >= n_batches) return;
+        const int c0 = b * kBatch, nch = min(kBatch, n_cells - c0);
+        cp_n = lane <= nch ? cell_ptr[c0 + lane] : 0;
+        g_n0 = lane < nch * 5 ? geom[(int64_t)c0 * 5 + lane] : 0.f;
+        g_n1 = lane + 64 < nch * 5 ? geom[(int64_t)c0 * 5 + lane + 64] : 0.f;
+    };
+    auto fetch_rows = [&](int b) {
+        if (b >= n_batches) return;
+        const int nch = min(kBatch, n_cells - b * kBatch);
+        const int R0 = uniform_l(__shfl(cp_n, 0, 64)), R1 = uniform_l(__shfl(cp_n, nch, 64));
+        const int nv = (R1 - R0) * NP;           // <= kBatchRows * NP (host-checked cells)
+#pragma unroll
+        for (int k = 0; k < kXv; ++k)
+            xv[k] = lane + 64 * k < nv ? x[(int64_t)R0 * NP + lane + 64 * k] : 0.0;
+        sp_n = lane < R1 - R0 ? row_species[R0 + lane] : 0;
+    };
+    const int stride = gridDim.x * 4;
+    int bt = uniform_l(blockIdx.x * 4 + w);
+    fetch_cells(bt);
+    fetch_rows(bt);
+    for (; bt < n_batches; bt += stride) {
+        const int c0 = bt * kBatch;
+        const int nch = min(kBatch, n_cells - c0);
+        const int R0 = uniform_l(__shfl(cp_n, 0, 64)), R1 = uniform_l(__shfl(cp_n, nch, 64));
+        const int nv = (R1 - R0) * NP;
+        if (lane <= nch) cps[w][lane] = cp_n;
+        if (lane < nch * 5) gs[w][lane] = g_n0;
+        if (lane + 64 < nch * 5) gs[w][lane + 64] = g_n1;
+#pragma unroll
+        for (int k = 0; k < kXv; ++k)
+            if (lane + 64 * k < nv) xs[w][lane + 64 * k] = xv[k];
+        if (lane < R1 - R0) spc[w][lane] = sp_n;
+        for (int e = lane; e < kBatch * 24; e += 64) reinterpret_cast<unsigned*>(&fa[w][0][0])[e] = 0u;
+        fetch_cells(bt + stride);
+        wave_sync_lds();
+        // per cell (four lanes each): Jacobi-step norm and the normalised features
+        const int gc = lane >> 2, sub = lane & 3;
+        int r0 = 0, nc = 0;
+        if (gc < nch) {
+            r0 = cps[w][gc] - R0;
+            nc = (cps[w][gc + 1] - R0 - r0) * NP;
+        }
+        double ss = 0.0;
+        for (int v = sub; v < nc; v += 4) {
+            const double j = xs[w][r0 * NP + v];
+            ss += j * j;
+        }
+        ss += __shfl_xor(ss, 1, 64);
+        ss += __shfl_xor(ss, 2, 64);
+        const double sc = sqrt(ss);
+        const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+        if (sub == 0 && gc < nch) scs[w][gc] = sc;
+        for (int v = sub; v < nc; v += 4) {
+            const int rr = v / NP;
+            fa[w][gc][spc[w][r0 + rr] * NP + (v - rr * NP)] =
+                to_bf16((float)(xs[w][r0 * NP + v] * inv));
+        }
+        if (gc < nch)
+            for (int e = sub; e < 5; e += 4) fa[w][gc][kOut + e] = to_bf16(gs[w][gc * 5 + e]);
+        fetch_rows(bt + stride);
+        wave_sync_lds();
+        // layer 1: [16 x 48] x [48 x 64]
+        f32x4_t acc[4];
+#pragma unroll
+        for (int t = 0; t < kT1; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < kQ1; ++q) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(&fa[w][li][16 * q + 4 * lk]);
+#pragma unroll
+            for (int t = 0; t < kT1; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B1[t * kQ1 + q], acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < kT1; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                ha[w][4 * lk + r][16 * t + li] = to_bf16(gelu_f(acc[t][r] + bb1[t]));
+        wave_sync_lds();
+        // layer 2: [16 x 64] x [64 x 64]
+#pragma unroll
+        for (int t = 0; t < kT2; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < kQ2; ++q) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(&ha[w][li][16 * q + 4 * lk]);
+#pragma unroll
+            for (int t = 0; t < kT2; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B2[t * kQ2 + q], acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < kT2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                hb[w][4 * lk + r][16 * t + li] = to_bf16(gelu_f(acc[t][r] + bb2[t]));
+        wave_sync_lds();
+        // layer 3: [16 x 64] x [64 x 48]
+#pragma unroll
+        for (int t = 0; t < kT3; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < kQ3; ++q) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(&hb[w][li][16 * q + 4 * lk]);
+#pragma unroll
+            for (int t = 0; t < kT3; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B3[t * kQ3 + q], acc[t], 0, 0, 0);
+        }
+        // guard from the accumulators: lane (li, lk) holds outputs 16 t + li of
+        // cells 4 lk + r; columns 40..47 are exactly zero (zero weights, bias)
+        float yy[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            yy[r] = 0.f;
+#pragma unroll
+            for (int t = 0; t < kT3; ++t) {
+                const float y = acc[t][r] + bb3[t];
+                ya[w][4 * lk + r][16 * t + li] = y;
+                yy[r] += y * y;
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) yy[r] += __shfl_xor(yy[r], off, 64);
+        if (li == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // a non-finite proposal gives a non-finite sum: NaN <= guard is false
+                const bool bad = !(sqrtf(yy[r]) <= guard);
+                badc[w][4 * lk + r] = bad;
+                if (bad && 4 * lk + r < nch) guarded += 1;
+            }
+        }
+        wave_sync_lds();
+        // per cell (four lanes each): x_c = j_c + s_c y_c unless guarded
+        if (gc < nch && !badc[w][gc]) {
+            const double scc = scs[w][gc];
+            for (int v = sub; v < nc; v += 4) {
+                const int rr = v / NP;
+                xs[w][r0 * NP + v] += scc * (double)ya[w][gc][spc[w][r0 + rr] * NP + (v - rr * NP)];
+            }
+        }
+        wave_sync_lds();
+        for (int e = lane; e < nv; e += 64) x[(int64_t)R0 * NP + e] = xs[w][e];
+        wave_sync_lds();
+    }
+    // lanes 0, 16, 32, 48 counted their cells
+    guarded += __shfl_xor(guarded, 16, 64);
+    guarded += __shfl_xor(guarded, 32, 64);
+    if (lane == 0 && guarded) atomicAdd(nguard, guarded);
+}
+
+// ---------------------------------------------------------------------------
 static inline unsigned nbk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int mlp_param_count() { return kParams; }
@@ -432,6 +670,21 @@ void launch_learned_correct(hipStream_t s, int n_cells, const int* cp, const int
     const int g = (int)std::min<int64_t>(nbk(chunks, 4), kInferBlocks);
     k_learned_correct<<<std::max(g, 1), 256, 0, s>>>(n_cells, cp, row_species, geom, params, guard,
                                                      x, nguard);
+}
+
+int mlp_packed_bf16_count() { return kPackedBf16; }
+
+void launch_pack_bf16(hipStream_t s, const float* params, unsigned short* out) {
+    k_pack_bf16<<<nbk(kPackedBf16, 256), 256, 0, s>>>(params, out);
+}
+
+void launch_learned_correct_bf16(hipStream_t s, int n_cells, const int* cp, const int* row_species,
+                                 const float* geom, const unsigned short* wpk,
+                                 const float* params, float guard, double* x, int* nguard) {
+    const int64_t batches = (n_cells + kBatch - 1) / kBatch;
+    const int g = (int)std::min<int64_t>(nbk(batches, 4), kInferBlocks);
+    k_learned_correct_bf16<<<std::max(g, 1), 256, 0, s>>>(n_cells, cp, row_species, geom, wpk,
+                                                          params, guard, x, nguard);
 }
 
 void launch_learned_features(hipStream_t s, int n_sel, int cell0, int cell_step, const int* cp,

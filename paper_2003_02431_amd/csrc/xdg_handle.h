@@ -116,6 +116,8 @@ struct xdg_handle {
     int* row_species = nullptr;
     float* cell_geom = nullptr;
     int* d_nguard = nullptr;
+    unsigned short* mlp_wbf = nullptr;   // bf16 MFMA operand tiles of the weights
+    bool wbf_stale = true;               // parameters changed since the last packing
     // orthonormalisation multigrid: per level the family Z, W = M Z, the
     // iterate, its residual, a work vector, and the family size
     std::vector<double*> omZ, omW, omX, omR, omT;

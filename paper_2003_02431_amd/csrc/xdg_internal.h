@@ -142,6 +142,12 @@ void launch_mlp_grad(hipStream_t s, int n, int n_total, int n_blocks, const floa
                      float* grad, float* loss);
 void launch_adam(hipStream_t s, float* w, const float* g, float* m, float* v, float lr, float b1,
                  float b2, float c1, float c2, float eps);
+// bf16 inference: weights packed into MFMA operand tiles
+int mlp_packed_bf16_count();
+void launch_pack_bf16(hipStream_t s, const float* params, unsigned short* out);
+void launch_learned_correct_bf16(hipStream_t s, int n_cells, const int* cp, const int* row_species,
+                                 const float* geom, const unsigned short* wpk,
+                                 const float* params, float guard, double* x, int* nguard);
 // x holds j = omega D^{-1} b (the plain first sweep); adds the learned part
 void launch_learned_correct(hipStream_t s, int n_cells, const int* cp, const int* row_species,
                             const float* geom, const float* params, float guard, double* x,

@@ -18,6 +18,7 @@ static int mlp_alloc(xdg_handle* h) {
     CHK(h->alloc(&h->mlp_ploss, (size_t)h->mlp_blocks * 4));
     CHK(h->alloc(&h->mlp_loss, 1));
     CHK(h->alloc(&h->d_nguard, 1));
+    CHK(h->alloc(&h->mlp_wbf, mlp_packed_bf16_count()));
     HIPCHK(hipMemsetAsync(h->d_nguard, 0, sizeof(int), h->s));
     return XDG_OK;
 }
@@ -29,7 +30,8 @@ static bool finite_f(const float* v, size_t n) {
 }
 
 bool learned_active(xdg_handle* h) {
-    return h->opt.smoother == XDG_LEARNED && h->learned_ready && !h->learned_off;
+    return (h->opt.smoother == XDG_LEARNED || h->opt.smoother == XDG_LEARNED_BF16) &&
+           h->learned_ready && !h->learned_off;
 }
 
 // First pre-smoothing sweep of level 0 from x = 0 with the network's proposal:
@@ -37,6 +39,15 @@ bool learned_active(xdg_handle* h) {
 void learned_first_sweep(xdg_handle* h, Level& lv) {
     launch_jacobi<double>(h->s, true, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff,
                           lv.D64, lv.b64, nullptr, lv.x64, h->opt.omega);
+    if (h->opt.smoother == XDG_LEARNED_BF16) {
+        if (h->wbf_stale) {
+            launch_pack_bf16(h->s, h->mlp_w, h->mlp_wbf);
+            h->wbf_stale = false;
+        }
+        launch_learned_correct_bf16(h->s, lv.n_cells, lv.cp, h->row_species, h->cell_geom,
+                                    h->mlp_wbf, h->mlp_w, h->guard, lv.x64, h->d_nguard);
+        return;
+    }
     launch_learned_correct(h->s, lv.n_cells, lv.cp, h->row_species, h->cell_geom, h->mlp_w,
                            h->guard, lv.x64, h->d_nguard);
 }
@@ -44,7 +55,8 @@ void learned_first_sweep(xdg_handle* h, Level& lv) {
 // learned-smoother requirements on the handle's configuration
 int learned_validate(const xdg_options* opt, int np0) {
     if (opt->smoother == XDG_JACOBI) return XDG_OK;
-    if (opt->smoother != XDG_LEARNED) return fail(XDG_EINVAL, "unknown smoother");
+    if (opt->smoother != XDG_LEARNED && opt->smoother != XDG_LEARNED_BF16)
+        return fail(XDG_EINVAL, "unknown smoother");
     if (np0 != 20 || opt->nrhs != 1 || opt->krylov != XDG_FGMRES ||
         opt->precision != XDG_FP64 || opt->nu_pre < 1)
         return fail(XDG_EINVAL,
@@ -67,6 +79,7 @@ extern "C" int xdg_mlp_set(xdg_handle* h, const float* params) {
     HIPCHK(hipMemsetAsync(h->mlp_v, 0, np * sizeof(float), h->s));
     HIPCHK(hipStreamSynchronize(h->s));
     h->mlp_step = 0;
+    h->wbf_stale = true;
     h->learned_ready = h->row_species != nullptr;
     return XDG_OK;
 }
@@ -121,6 +134,7 @@ extern "C" int xdg_mlp_train(xdg_handle* h, int32_t n, const float* X, const flo
         launch_adam(h->s, h->mlp_w, h->mlp_g, h->mlp_m, h->mlp_v, lr, (float)b1, (float)b2, c1, c2,
                     1e-8f);
     }
+    if (steps > 0) h->wbf_stale = true;
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->s));
     return XDG_OK;

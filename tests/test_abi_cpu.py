@@ -98,6 +98,7 @@ def test_learned_smoother_requirements_and_null_calls():
     # np = 3: the learned smoother needs np = 20, FGMRES, FP64, one column
     for opt in (B.options(krylov=B.XDG_FGMRES, smoother=B.XDG_LEARNED),
                 B.options(krylov=B.XDG_CG, smoother=B.XDG_LEARNED),
+                B.options(krylov=B.XDG_FGMRES, smoother=B.XDG_LEARNED_BF16),
                 B.options(krylov=B.XDG_FGMRES, smoother=7)):
         with pytest.raises(B.XdgError) as e:
             B.xdg_create(rp, ci, val, cp, [], opt)

@@ -12,7 +12,9 @@ Tolerances (FP32 network against the FP64 oracle):
   * pairs: the features and targets are FP64 values rounded once to FP32:
     relative 2^-23 plus the FP64 summation-order differences;
   * learned V-cycle: the FP32 network output enters scaled by the Jacobi
-    step norm: relative 1e-5.
+    step norm: relative 1e-5;
+  * bf16 learned V-cycle against the oracle's bf16 emulation: relative 5e-6
+    and at most a tenth of its distance from the FP64 network.
 """
 import sys
 import time
@@ -216,6 +218,40 @@ def test_learned_vcycle_and_guard(torch):
     S.close()
 
 
+def test_bf16_learned_vcycle(torch):
+    """The bf16 matrix-core network inside the V-cycle against the oracle's
+    bf16 emulation (bf16 operands, FP64 sums): both round the same values to
+    bf16, so they differ only where an FP32 sum lands on the other side of a
+    bf16 rounding boundary -- far below the distance of either from the
+    FP64 network (about 5e-5 here).  A parameter change repacks the weights:
+    oversized proposals then give the plain V-cycle with every cell guarded."""
+    from oracle import learned, mg
+    from paper_2003_02431_amd import binding as B
+    pr, rs, g, S = _solver(41, torch, smoother=B.XDG_LEARNED_BF16)
+    H = mg.hierarchy_of(pr)
+    r = np.random.default_rng(8).uniform(-1, 1, pr.b.size)
+    th = _params(4, 0.05)
+    B.xdg_mlp_set(S.h, th)
+    z = S.vec(0)
+    g0 = B.xdg_learned_stats(S.h)[0]
+    B.xdg_vcycle(S.h, S.vec(0, r), z)
+    G = g.astype(np.float64)
+    ref = learned.vcycle(H, rs, G, th, r, S.guard, bf16=True)
+    ref64 = learned.vcycle(H, rs, G, th, r, S.guard)
+    e, d = _rel(z.cpu().numpy(), ref), _rel(ref, ref64)
+    _log(f"  bf16 learned V-cycle rel err {e:.2e} (bf16 vs FP64 network {d:.2e})")
+    assert e <= 5e-6 and d >= 1e-5 and e <= 0.1 * d
+    assert B.xdg_learned_stats(S.h)[0] == g0
+    plain = H.vcycle(r)
+    B.xdg_mlp_set(S.h, _params(4, 1e4))
+    B.xdg_vcycle(S.h, S.vec(0, r), z)
+    e = _rel(z.cpu().numpy(), plain)
+    guarded = B.xdg_learned_stats(S.h)[0] - g0
+    _log(f"  bf16 all-guarded V-cycle vs plain rel err {e:.2e}, guarded cells {guarded}")
+    assert e <= 1e-11 and guarded == S.n_cells
+    S.close()
+
+
 def _xstar(pr):
     from oracle import mg
     H = mg.hierarchy_of(pr)
@@ -301,7 +337,8 @@ def test_training_and_gain(torch):
     S.set_smoother(B.XDG_LEARNED, guard=GUARD)
     b = S.vec(0, pr.b)
     res = {}
-    for name, sm in (("plain", B.XDG_JACOBI), ("learned", B.XDG_LEARNED)):
+    for name, sm in (("plain", B.XDG_JACOBI), ("learned", B.XDG_LEARNED),
+                     ("learned_bf16", B.XDG_LEARNED_BF16)):
         S.set_smoother(sm)
         x = S.vec(0)
         torch.cuda.synchronize()
