@@ -14,16 +14,28 @@ namespace xdg {
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// row-major blocks in, column-major blocks out, staged through LDS so that
+// both the reads and the writes are contiguous (bpg blocks per group, at
+// most 32 KB of LDS)
+static inline int transpose_bpg(int np) {
+    return std::max(1, std::min(8, 32768 / (np * np * (int)sizeof(double))));
+}
 template <typename T>
-__global__ void k_transpose_blocks(int64_t nnzb, int np, const double* __restrict__ in,
-                                   T* __restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nb2 = (int64_t)np * np;
-    if (t >= nnzb * nb2) return;
-    const int64_t b = t / nb2;
-    const int e = (int)(t - b * nb2);
-    const int c = e / np, r = e - c * np;          // output: column-major
-    out[t] = (T)in[b * nb2 + (int64_t)r * np + c];  // input: row-major
+__global__ __launch_bounds__(256) void k_transpose_blocks(int64_t nnzb, int np, int bpg,
+                                                          const double* __restrict__ in,
+                                                          T* __restrict__ out) {
+    extern __shared__ double tile[];
+    const int nb2 = np * np;
+    const int64_t b0 = (int64_t)blockIdx.x * bpg;
+    const int nb = (int)min<int64_t>(bpg, nnzb - b0);
+    const int64_t base = b0 * nb2;
+    for (int e = threadIdx.x; e < nb * nb2; e += blockDim.x) tile[e] = in[base + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * nb2; e += blockDim.x) {
+        const int b = e / nb2, f = e - b * nb2;
+        const int c = f / np, r = f - c * np;          // output: column-major
+        out[base + e] = (T)tile[b * nb2 + r * np + c];
+    }
 }
 
 __global__ void k_extract_leading(int64_t nnzb, int npf, int npc, const double* __restrict__ A,
@@ -120,6 +132,36 @@ __device__ void gj_lds(double* a, int n, int* err) {
     __syncthreads();
 }
 
+// The same elimination for a compile-time order N and 256 threads (constant
+// index arithmetic, a fixed number of elements per thread).
+template <int N>
+__device__ void gj_lds_fixed(double* a, int* err) {
+    constexpr int kPer = (N * N + 255) / 256;
+    static_assert(N <= 256, "one thread per row/column entry in the scaling step");
+    for (int k = 0; k < N; ++k) {
+        __syncthreads();
+        const double piv = a[k * N + k];
+        if (!(piv > 0.0) && threadIdx.x == 0) *err = 1;
+        const double ip = 1.0 / piv;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = (int)threadIdx.x + 256 * q;
+            if (N * N % 256 == 0 || e < N * N) {
+                const int j = e / N, i = e - j * N;
+                if (i != k && j != k) a[e] -= a[k * N + i] * a[j * N + k] * ip;
+            }
+        }
+        __syncthreads();
+        const int e = threadIdx.x;
+        if (e < N && e != k) {
+            a[e * N + k] *= ip;                 // row k
+            a[k * N + e] = -a[k * N + e] * ip;  // column k
+        }
+        if (threadIdx.x == 0) a[k * N + k] = ip;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_gj_batched(int n_mats, const int64_t* __restrict__ doff,
                                                     const int* __restrict__ cell_ptr, int np,
                                                     double* __restrict__ D, int* err) {
@@ -129,7 +171,12 @@ __global__ __launch_bounds__(256) void k_gj_batched(int n_mats, const int64_t* _
     const int n = (cell_ptr[c + 1] - cell_ptr[c]) * np;
     double* Dc = D + doff[c];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) sm[e] = Dc[e];
-    gj_lds(sm, n, err);
+    if (n == 20)
+        gj_lds_fixed<20>(sm, err);
+    else if (n == 40)
+        gj_lds_fixed<40>(sm, err);
+    else
+        gj_lds(sm, n, err);
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) Dc[e] = sm[e];
 }
 
@@ -176,7 +223,7 @@ __global__ __launch_bounds__(256) void k_cgj_pivot(int K, int ld, const double* 
         const int r = e / NB, c = e - r * NB;
         a[c * NB + r] = A[(int64_t)(K * NB + r) * ld + K * NB + c];   // column-major in LDS
     }
-    gj_lds(a, NB, err);
+    gj_lds_fixed<NB>(a, err);
     for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
         const int r = e / NB, c = e - r * NB;
         P[e] = a[c * NB + r];                                          // row-major out
@@ -199,11 +246,22 @@ __global__ __launch_bounds__(256) void k_cgj_row(int nt, int K, int ld, double* 
     }
 }
 
-// A_IJ <- A_IJ - A_IK A_KJ for I, J != K (row K already updated)
-__global__ __launch_bounds__(256) void k_cgj_update(int nt, int K, int ld, double* __restrict__ A) {
+// A_IJ <- A_IJ - A_IK A_KJ for I, J != K (row K already updated).  When a
+// next panel exists, the group that updates its pivot tile A_{K+1,K+1} is
+// dispatched first and also inverts that tile into Pn (the next panel's P),
+// so the pivot inversion overlaps the rest of the update.
+__global__ __launch_bounds__(256) void k_cgj_update(int nt, int K, int ld, double* __restrict__ A,
+                                                    double* __restrict__ Pn, int* err) {
     __shared__ double u[NB][NB + 1], v[NB][NB + 1];
+    __shared__ double a[NB * NB];
     const int m = nt - 1;
-    const int Ip = blockIdx.x / m, Jp = blockIdx.x - Ip * m;
+    int t = blockIdx.x;
+    const bool next = K + 1 < nt;
+    if (next) {
+        const int tn = K * m + K;          // reduced index of (K+1, K+1)
+        t = t == 0 ? tn : (t == tn ? 0 : t);
+    }
+    const int Ip = t / m, Jp = t - Ip * m;
     const int I = Ip + (Ip >= K ? 1 : 0), J = Jp + (Jp >= K ? 1 : 0);
     load_tile(u, A, ld, I, K);
     load_tile(v, A, ld, K, J);
@@ -216,8 +274,22 @@ __global__ __launch_bounds__(256) void k_cgj_update(int nt, int K, int ld, doubl
 #pragma unroll
         for (int q = 0; q < 4; ++q) s[q] += u[r0 + q][k] * vk;
     }
+    double nv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) A[(int64_t)(I * NB + r0 + q) * ld + J * NB + c] -= s[q];
+    for (int q = 0; q < 4; ++q) {
+        double* dst = &A[(int64_t)(I * NB + r0 + q) * ld + J * NB + c];
+        nv[q] = *dst - s[q];
+        *dst = nv[q];
+    }
+    if (next && I == K + 1 && J == K + 1) {      // uniform over the group
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[c * NB + r0 + q] = nv[q];   // column-major
+        gj_lds_fixed<NB>(a, err);
+        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+            const int r = e / NB, cc = e - r * NB;
+            Pn[e] = a[cc * NB + r];                                // row-major out
+        }
+    }
 }
 
 // column K: A_IK <- -A_IK P for I != K ; A_KK <- P
@@ -250,8 +322,9 @@ __global__ void k_convert(int64_t n, const Tin* __restrict__ in, Tout* __restric
 // ---------------------------------------------------------------------------
 template <typename T>
 void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* in, T* out) {
-    const int64_t n = nnzb * np * np;
-    k_transpose_blocks<T><<<nblk(n, 256), 256, 0, s>>>(nnzb, np, in, out);
+    const int bpg = transpose_bpg(np);
+    const size_t lds = (size_t)bpg * np * np * sizeof(double);
+    k_transpose_blocks<T><<<nblk(nnzb, bpg), 256, lds, s>>>(nnzb, np, bpg, in, out);
 }
 void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const double* A,
                             double* Ac) {
@@ -275,11 +348,15 @@ void launch_bsr_to_dense(hipStream_t s, int n_rows, int np, const int* rp, const
                          const double* A, int ld, int npad, double* dense) {
     k_bsr_to_dense<<<n_rows + 1, 256, 0, s>>>(n_rows, np, rp, ci, A, ld, npad, dense);
 }
-void launch_coarse_gj_step(hipStream_t s, int nt, int K, int ld, double* A, double* P, int* err) {
-    k_cgj_pivot<<<1, 256, 0, s>>>(K, ld, A, P, err);
+void launch_coarse_gj_step(hipStream_t s, int nt, int K, int ld, double* A, double* P2, int* err) {
+    // P2 holds two pivot inverses: panel K uses P2[K % 2]; the update of
+    // panel K writes the inverse for panel K + 1 into the other half
+    double* P = P2 + (K & 1) * NB * NB;
+    double* Pn = P2 + ((K + 1) & 1) * NB * NB;
+    if (K == 0) k_cgj_pivot<<<1, 256, 0, s>>>(K, ld, A, P, err);
     if (nt > 1) {
         k_cgj_row<<<nt - 1, 256, 0, s>>>(nt, K, ld, A, P);
-        k_cgj_update<<<(nt - 1) * (nt - 1), 256, 0, s>>>(nt, K, ld, A);
+        k_cgj_update<<<(nt - 1) * (nt - 1), 256, 0, s>>>(nt, K, ld, A, Pn, err);
     }
     k_cgj_col<<<nt, 256, 0, s>>>(nt, K, ld, A, P);
 }

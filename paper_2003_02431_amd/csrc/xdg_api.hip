@@ -445,7 +445,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
         h->cn = lc.n_rows * lc.np;
         h->cld = ((h->cn + kCoarseNB - 1) / kCoarseNB) * kCoarseNB;
         CHK(h->alloc(&h->Cinv, (size_t)h->cld * h->cld));
-        CHK(h->alloc(&h->Pbuf, kCoarseNB * kCoarseNB));
+        CHK(h->alloc(&h->Pbuf, 2 * kCoarseNB * kCoarseNB));
     }
     for (auto& lv : h->L) CHK(setup_vectors(h, lv, h->mixed));
     const int64_t n0 = L0.len();

@@ -93,7 +93,7 @@ struct xdg_handle {
     std::vector<Level> L;
     int cn = 0, cld = 0;            // coarsest order, padded leading dimension
     double* Cinv = nullptr;
-    double* Pbuf = nullptr;         // pivot tile of the coarse inversion
+    double* Pbuf = nullptr;         // pivot-tile inverses of the coarse inversion (two panels)
     double* scal = nullptr;         // device scalars
     double* part = nullptr;         // reduction partials
     double* h_scal = nullptr;       // pinned host mirror
