@@ -252,6 +252,37 @@ def test_bf16_learned_vcycle(torch):
     S.close()
 
 
+def test_ragged_tail_learned_vcycle(torch):
+    """4,068 cells (not a multiple of the 16-cell bf16 batch or the 8-cell
+    FP32 chunk): a residual supported on the last 8 cells only, so that the
+    V-cycle differs from the plain one only through the tail's corrections;
+    both networks against the oracle."""
+    from oracle import learned, mg
+    from paper_2003_02431_amd import binding as B
+    pr, rs, g, S = _solver(47, torch)
+    assert S.n_cells % 16 == 4 and S.n_cells % 8 == 4
+    H = mg.hierarchy_of(pr)
+    cp = np.asarray(pr.cell_ptr)
+    r = np.zeros(pr.b.size)
+    tail = slice(cp[-9] * pr.np, cp[-1] * pr.np)
+    r[tail] = np.random.default_rng(9).uniform(-1, 1, r[tail].size)
+    th = _params(4, 0.05)
+    B.xdg_mlp_set(S.h, th)
+    G = g.astype(np.float64)
+    plain = H.vcycle(r)
+    for sm, bf, tol in ((B.XDG_LEARNED, False, 1e-5), (B.XDG_LEARNED_BF16, True, 5e-6)):
+        S.set_smoother(sm)
+        z = S.vec(0)
+        g0 = B.xdg_learned_stats(S.h)[0]
+        B.xdg_vcycle(S.h, S.vec(0, r), z)
+        ref = learned.vcycle(H, rs, G, th, r, S.guard, bf16=bf)
+        e, d = _rel(z.cpu().numpy(), ref), _rel(ref, plain)
+        _log(f"  ragged tail ({S.n_cells} cells), smoother {sm}: rel err {e:.2e} "
+             f"(learned vs plain {d:.2e})")
+        assert e <= tol and d >= 1e-3 and B.xdg_learned_stats(S.h)[0] == g0
+    S.close()
+
+
 def _xstar(pr):
     from oracle import mg
     H = mg.hierarchy_of(pr)
