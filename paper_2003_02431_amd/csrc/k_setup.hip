@@ -59,23 +59,47 @@ __global__ __launch_bounds__(64) void k_galerkin_dense(int n_cblk, int npf, int 
                                                        const double* __restrict__ A,
                                                        const double* __restrict__ R,
                                                        double* __restrict__ Ac) {
+    __shared__ double part[64];
     const int cb = blockIdx.x;
     if (cb >= n_cblk) return;
     const int nc2 = npc * npc;
-    for (int t = threadIdx.x; t < nc2; t += blockDim.x) {
-        const int m2 = t / npc, m = t - m2 * npc;
+    const int k0 = cptr[cb], k1 = cptr[cb + 1];
+    auto term = [&](int k, int m, int m2) {
+        const double* Ab = A + (int64_t)cfb[k] * npf * npf;      // column-major
+        const double* Ri = R + (int64_t)crow[k] * npf * npc;
+        const double* Rl = R + (int64_t)ccol[k] * npf * npc;
         double acc = 0.0;
-        for (int k = cptr[cb]; k < cptr[cb + 1]; ++k) {
-            const double* Ab = A + (int64_t)cfb[k] * npf * npf;      // column-major
-            const double* Ri = R + (int64_t)crow[k] * npf * npc;
-            const double* Rl = R + (int64_t)ccol[k] * npf * npc;
-            for (int b = 0; b < npf; ++b) {
-                double s = 0.0;
-                for (int a = 0; a < npf; ++a) s += Ri[a * npc + m] * Ab[b * npf + a];
-                acc += s * Rl[b * npc + m2];
-            }
+        for (int b = 0; b < npf; ++b) {
+            double s = 0.0;
+            for (int a = 0; a < npf; ++a) s += Ri[a * npc + m] * Ab[b * npf + a];
+            acc += s * Rl[b * npc + m2];
         }
-        Ac[(int64_t)cb * nc2 + t] = acc;
+        return acc;
+    };
+    if (nc2 > 32) {
+        for (int t = threadIdx.x; t < nc2; t += blockDim.x) {
+            const int m2 = t / npc, m = t - m2 * npc;
+            double acc = 0.0;
+            for (int k = k0; k < k1; ++k) acc += term(k, m, m2);
+            Ac[(int64_t)cb * nc2 + t] = acc;
+        }
+        return;
+    }
+    // small coarse blocks: G groups of nc2 threads take every G-th fine
+    // contribution; the G partial sums are added in group order
+    const int G = 64 / nc2;
+    const int g = threadIdx.x / nc2, t = threadIdx.x - g * nc2;
+    double acc = 0.0;
+    if (g < G) {
+        const int m2 = t / npc, m = t - m2 * npc;
+        for (int k = k0 + g; k < k1; k += G) acc += term(k, m, m2);
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < nc2) {
+        double sum = 0.0;
+        for (int q = 0; q < G; ++q) sum += part[q * nc2 + threadIdx.x];
+        Ac[(int64_t)cb * nc2 + threadIdx.x] = sum;
     }
 }
 
