@@ -197,6 +197,9 @@ def bench_multi_rhs(args):
         fl = 2.0 * nnzb * pr.np ** 2 * 16
         res[name] = dict(us=round(t * 1e6, 1), gbs=round(byt / t / 1e9, 1),
                          tflops=round(fl / t / 1e12, 2), mfma_frac=round(fl / t / 1e12 / peak, 3))
+        if prec == B.XDG_MIXED:
+            res[name]["note"] = ("API call: includes the FP64->FP32 conversion of X and the "
+                                 "FP32->FP64 conversion of Y around the FP32 MFMA kernel")
         log(f"[bench-c4] spmm {name}: {res[name]}")
     # one column alone through the single-right-hand-side mixed path, for the ratio
     S1 = None
