@@ -169,6 +169,21 @@ int xdg_get_cell_inverse(xdg_handle *h, int32_t level, int32_t cell, double *out
  * the stream; returns XDG_ENOTSPD on a non-positive pivot. */
 int xdg_update_matrix(xdg_handle *h, const double *val_dev);
 
+/* Partial form of xdg_update_matrix for new values that differ from the
+ * current ones only in the block rows and block columns of the listed level-0
+ * smoother cells -- the cut cells of an interface that moves without changing
+ * the agglomeration (Section 3.1: the hierarchy's operators are computed once
+ * on the background mesh and renewed only in cut cells).  val_dev holds all
+ * level-0 values, laid out as for xdg_update_matrix.  Only the affected blocks
+ * are re-laid out, only the Galerkin blocks and cell-block inverses they reach
+ * are recomputed on every level; the coarsest inverse is rebuilt.  When the
+ * values outside those rows and columns are unchanged the result equals
+ * xdg_update_matrix's bit for bit.  cells_host: n >= 1 distinct indices in
+ * [0, n_cells).  Single-column handles (nrhs = 1).  Synchronises the stream;
+ * XDG_ENOTSPD on a non-positive pivot. */
+int xdg_update_cells(xdg_handle *h, const double *val_dev, int32_t n,
+                     const int32_t *cells_host);
+
 /* New stopping rule for later xdg_solve calls: rtol > 0, maxit >= 1. */
 int xdg_set_tolerance(xdg_handle *h, double rtol, int32_t maxit);
 

@@ -69,6 +69,7 @@ def _load():
         "xdg_get_level_matrix": ([vp, C.c_int32, _i32p, _i32p, _f64p], C.c_int),
         "xdg_get_cell_inverse": ([vp, C.c_int32, C.c_int32, _f64p, C.c_int32, _i32p], C.c_int),
         "xdg_update_matrix": ([vp, vp], C.c_int),
+        "xdg_update_cells": ([vp, vp, C.c_int32, _i32p], C.c_int),
         "xdg_spmm": ([vp, C.c_int32, C.c_int32, vp, vp], C.c_int),
         "xdg_setup_time": ([vp, _f64p], C.c_int),
         "xdg_mlp_param_count": ([], C.c_int32),
@@ -97,7 +98,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("xdg_create", "xdg_spmv", "xdg_smooth", "xdg_restrict", "xdg_prolong",
             "xdg_vcycle", "xdg_solve", "xdg_level_info", "xdg_get_level_matrix",
-            "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_spmm", "xdg_setup_time",
+            "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_update_cells", "xdg_spmm", "xdg_setup_time",
             "xdg_mlp_param_count", "xdg_mlp_set", "xdg_mlp_get", "xdg_mlp_forward",
             "xdg_mlp_gradient", "xdg_mlp_train", "xdg_set_cell_features", "xdg_learned_pairs",
             "xdg_set_smoother", "xdg_learned_stats", "xdg_set_tolerance", "xdg_destroy",
@@ -231,6 +232,13 @@ def xdg_spmm(h, level, precision, X, Y):
 
 def xdg_update_matrix(h, val_dev):
     return _check(_lib.xdg_update_matrix(h, _ptr(val_dev)))
+
+
+def xdg_update_cells(h, val_dev, cells):
+    """New level-0 values changed only in the rows/columns of `cells`."""
+    c = np.ascontiguousarray(cells, dtype=np.int32)
+    return _check(_lib.xdg_update_cells(h, _ptr(val_dev), int(c.size),
+                                        c.ctypes.data_as(_i32p)))
 
 
 def xdg_setup_time(h):

@@ -38,6 +38,35 @@ __global__ __launch_bounds__(256) void k_transpose_blocks(int64_t nnzb, int np, 
     }
 }
 
+// the same two layout steps for a list of blocks (one group per listed block)
+__global__ __launch_bounds__(256) void k_transpose_list(int n, const int* __restrict__ list,
+                                                        int np, const double* __restrict__ in,
+                                                        double* __restrict__ out) {
+    extern __shared__ double tile[];
+    if ((int)blockIdx.x >= n) return;
+    const int nb2 = np * np;
+    const int64_t base = (int64_t)list[blockIdx.x] * nb2;
+    for (int e = threadIdx.x; e < nb2; e += blockDim.x) tile[e] = in[base + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb2; e += blockDim.x) {
+        const int c = e / np, r = e - c * np;
+        out[base + e] = tile[r * np + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_extract_list(int n, const int* __restrict__ list,
+                                                      int npf, int npc,
+                                                      const double* __restrict__ A,
+                                                      double* __restrict__ Ac) {
+    if ((int)blockIdx.x >= n) return;
+    const int64_t b = list[blockIdx.x];
+    const int nc2 = npc * npc;
+    for (int e = threadIdx.x; e < nc2; e += blockDim.x) {
+        const int c = e / npc, r = e - c * npc;
+        Ac[b * nc2 + e] = A[b * npf * npf + (int64_t)c * npf + r];
+    }
+}
+
 __global__ void k_extract_leading(int64_t nnzb, int npf, int npc, const double* __restrict__ A,
                                   double* __restrict__ Ac) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,10 +87,11 @@ __global__ __launch_bounds__(64) void k_galerkin_dense(int n_cblk, int npf, int 
                                                        const int* __restrict__ ccol,
                                                        const double* __restrict__ A,
                                                        const double* __restrict__ R,
-                                                       double* __restrict__ Ac) {
+                                                       double* __restrict__ Ac,
+                                                       const int* __restrict__ list) {
     __shared__ double part[64];
-    const int cb = blockIdx.x;
-    if (cb >= n_cblk) return;
+    if ((int)blockIdx.x >= n_cblk) return;
+    const int cb = list ? list[blockIdx.x] : (int)blockIdx.x;
     const int nc2 = npc * npc;
     const int k0 = cptr[cb], k1 = cptr[cb + 1];
     auto term = [&](int k, int m, int m2) {
@@ -111,12 +141,17 @@ __global__ __launch_bounds__(256) void k_gather_cells(int n_cells, int np,
                                                       const int* __restrict__ ci,
                                                       const double* __restrict__ A,
                                                       const int64_t* __restrict__ doff,
-                                                      double* __restrict__ D) {
-    const int c = blockIdx.x;
-    if (c >= n_cells) return;
+                                                      double* __restrict__ D,
+                                                      const int* __restrict__ list) {
+    if ((int)blockIdx.x >= n_cells) return;
+    const int c = list ? list[blockIdx.x] : (int)blockIdx.x;
     const int r0 = cell_ptr[c], r1 = cell_ptr[c + 1];
     const int nc = (r1 - r0) * np;
-    double* Dc = D + doff[c];        // zero-filled by the caller
+    double* Dc = D + doff[c];        // zero-filled by the caller (whole array) or here (list)
+    if (list) {
+        for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) Dc[e] = 0.0;
+        __syncthreads();
+    }
     const int np2 = np * np;
     for (int row = r0; row < r1; ++row) {
         for (int blk = rp[row]; blk < rp[row + 1]; ++blk) {
@@ -188,10 +223,11 @@ __device__ void gj_lds_fixed(double* a, int* err) {
 
 __global__ __launch_bounds__(256) void k_gj_batched(int n_mats, const int64_t* __restrict__ doff,
                                                     const int* __restrict__ cell_ptr, int np,
-                                                    double* __restrict__ D, int* err) {
+                                                    double* __restrict__ D, int* err,
+                                                    const int* __restrict__ list) {
     extern __shared__ double sm[];
-    const int c = blockIdx.x;
-    if (c >= n_mats) return;
+    if ((int)blockIdx.x >= n_mats) return;
+    const int c = list ? list[blockIdx.x] : (int)blockIdx.x;
     const int n = (cell_ptr[c + 1] - cell_ptr[c]) * np;
     double* Dc = D + doff[c];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) sm[e] = Dc[e];
@@ -356,17 +392,30 @@ void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const
 }
 void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
                            const int* cfb, const int* crow, const int* ccol, const double* A,
-                           const double* R, double* Ac) {
-    k_galerkin_dense<<<n_cblk, 64, 0, s>>>(n_cblk, npf, npc, cptr, cfb, crow, ccol, A, R, Ac);
+                           const double* R, double* Ac, const int* list) {
+    if (n_cblk > 0)
+        k_galerkin_dense<<<n_cblk, 64, 0, s>>>(n_cblk, npf, npc, cptr, cfb, crow, ccol, A, R, Ac,
+                                               list);
+}
+void launch_transpose_list(hipStream_t s, int n, const int* list, int np, const double* in,
+                           double* out) {
+    if (n > 0)
+        k_transpose_list<<<n, 256, (size_t)np * np * sizeof(double), s>>>(n, list, np, in, out);
+}
+void launch_extract_list(hipStream_t s, int n, const int* list, int npf, int npc,
+                         const double* A, double* Ac) {
+    if (n > 0) k_extract_list<<<n, 256, 0, s>>>(n, list, npf, npc, A, Ac);
 }
 void launch_gather_cells(hipStream_t s, int n_cells, int np, const int* cell_ptr, const int* rp,
-                         const int* ci, const double* A, const int64_t* doff, double* D) {
-    k_gather_cells<<<n_cells, 256, 0, s>>>(n_cells, np, cell_ptr, rp, ci, A, doff, D);
+                         const int* ci, const double* A, const int64_t* doff, double* D,
+                         const int* list) {
+    if (n_cells > 0)
+        k_gather_cells<<<n_cells, 256, 0, s>>>(n_cells, np, cell_ptr, rp, ci, A, doff, D, list);
 }
 void launch_gj_batched(hipStream_t s, int n_mats, const int64_t* doff, const int* cell_ptr,
-                       int np, int max_n, double* D, int* err) {
+                       int np, int max_n, double* D, int* err, const int* list) {
     const size_t lds = (size_t)max_n * max_n * sizeof(double);
-    k_gj_batched<<<n_mats, 256, lds, s>>>(n_mats, doff, cell_ptr, np, D, err);
+    if (n_mats > 0) k_gj_batched<<<n_mats, 256, lds, s>>>(n_mats, doff, cell_ptr, np, D, err, list);
 }
 void launch_bsr_to_dense(hipStream_t s, int n_rows, int np, const int* rp, const int* ci,
                          const double* A, int ld, int npad, double* dense) {

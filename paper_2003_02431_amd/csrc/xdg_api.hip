@@ -111,6 +111,7 @@ static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* p
         }
     std::stable_sort(it.begin(), it.end(), [](const Item& a, const Item& b) { return a.key < b.key; });
     std::vector<int> cptr, cfb(it.size()), crow(it.size()), ccol(it.size());
+    f.h_fb2cb.assign(f.nnzb, -1);
     c.h_rp.assign(ncr + 1, 0);
     c.h_ci.clear();
     for (size_t k = 0; k < it.size(); ++k) {
@@ -121,6 +122,7 @@ static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* p
             c.h_rp[row + 1]++;
         }
         cfb[k] = it[k].fb;
+        f.h_fb2cb[it[k].fb] = (int)cptr.size() - 1;
         crow[k] = it[k].i;
         ccol[k] = it[k].l;
     }
@@ -140,8 +142,10 @@ static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* p
 
 static int invert_cells(xdg_handle* h, Level& lv) {
     HIPCHK(hipMemsetAsync(lv.D64, 0, lv.dsize * sizeof(double), h->s));
-    launch_gather_cells(h->s, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff, lv.D64);
-    launch_gj_batched(h->s, lv.n_cells, lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64, h->d_err);
+    launch_gather_cells(h->s, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff, lv.D64,
+                        nullptr);
+    launch_gj_batched(h->s, lv.n_cells, lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64, h->d_err,
+                      nullptr);
     HIPCHK(hipGetLastError());
     return XDG_OK;
 }
@@ -172,7 +176,7 @@ static int numeric_setup(xdg_handle* h, const double* raw) {
             launch_extract_leading(s, f.nnzb, f.np, c.np, f.A64, c.A64);
         else
             launch_galerkin_dense(s, c.nnzb, f.np, c.np, f.g_ptr, f.g_fb, f.g_row, f.g_col,
-                                  f.A64, f.R64, c.A64);
+                                  f.A64, f.R64, c.A64, nullptr);
     }
     for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l]));
     CHK(invert_coarsest(h, h->L[nl - 1]));
@@ -311,6 +315,7 @@ extern "C" void xdg_destroy(xdg_handle* h) {
     if (h->s) (void)hipStreamSynchronize(h->s);
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
+    if (h->h_stage) (void)hipHostFree(h->h_stage);
     delete h;
 }
 
@@ -840,6 +845,144 @@ extern "C" int xdg_update_matrix(xdg_handle* h, const double* val_dev) {
     if (!h || !val_dev) return fail(XDG_EINVAL, "xdg_update_matrix: NULL argument");
     CHK(numeric_setup(h, val_dev));
     return check_setup_error(h);
+}
+
+// Partial numeric set-up: the level-0 values changed only in the block rows
+// and block columns of the listed smoother cells.  Affected sets, level by
+// level: the level-0 blocks in those rows and their transposed blocks; a
+// p-truncated level keeps the block indices; an aggregation level takes the
+// coarse blocks the affected fine blocks contribute to; a cell is re-inverted
+// when one of its diagonal-cell blocks is affected.  The same kernels as the
+// full set-up run on the listed blocks and cells, so the result equals the
+// full set-up's.  Host work is proportional to the affected sets (the maps
+// below are built once per handle).
+static int update_prepare(xdg_handle* h) {
+    if (h->h_stage) return XDG_OK;
+    int64_t total = 0;
+    for (auto& lv : h->L) {
+        lv.h_rob.resize(lv.nnzb);
+        for (int i = 0; i < lv.n_rows; ++i)
+            for (int b = lv.h_rp[i]; b < lv.h_rp[i + 1]; ++b) lv.h_rob[b] = i;
+        lv.h_cor.assign(lv.n_rows, -1);
+        for (int c = 0; c < lv.n_cells; ++c)
+            for (int r = lv.h_cp[c]; r < lv.h_cp[c + 1]; ++r) lv.h_cor[r] = c;
+        lv.h_bmark.assign(lv.nnzb, 0);
+        lv.h_cmark.assign(std::max(lv.n_cells, 1), 0);
+        total += lv.nnzb + lv.n_cells;
+    }
+    Level& L0 = h->L[0];
+    L0.h_btr.assign(L0.nnzb, -1);
+    for (int b = 0; b < L0.nnzb; ++b) {
+        const int i = L0.h_rob[b], l = L0.h_ci[b];
+        for (int e = L0.h_rp[l]; e < L0.h_rp[l + 1]; ++e)
+            if (L0.h_ci[e] == i) L0.h_btr[b] = e;
+        if (L0.h_btr[b] < 0)
+            return fail(XDG_EINVAL, "xdg_update_cells: the level-0 pattern is not symmetric");
+    }
+    HIPCHK(hipHostMalloc((void**)&h->h_stage, std::max<int64_t>(total, 1) * sizeof(int),
+                         hipHostMallocDefault));
+    CHK(h->alloc(&h->d_stage, (size_t)std::max<int64_t>(total, 1)));
+    h->stage_len = total;
+    return XDG_OK;
+}
+
+extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
+                                const int32_t* cells) {
+    if (!h || !val_dev || n < 1 || !cells)
+        return fail(XDG_EINVAL, "xdg_update_cells: NULL argument or n < 1");
+    if (h->nrhs != 1)
+        return fail(XDG_EINVAL, "xdg_update_cells: single-column handles only (use "
+                                "xdg_update_matrix)");
+    Level& L0 = h->L[0];
+    for (int k = 0; k < n; ++k)
+        if (cells[k] < 0 || cells[k] >= L0.n_cells)
+            return fail(XDG_EINVAL, "xdg_update_cells: cell index out of range");
+    CHK(update_prepare(h));
+    {   // repeated cells
+        std::vector<int32_t> sorted(cells, cells + n);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(XDG_EINVAL, "xdg_update_cells: repeated cell");
+    }
+    const int nl = (int)h->L.size();
+    // host lists, level by level, written straight into the pinned stage
+    int* stage = h->h_stage;
+    int64_t used = 0;
+    std::vector<int64_t> boff(nl), bcnt(nl), coff(nl), ccnt(nl);
+    std::vector<int> cur, nxt;
+    for (int c = 0; c < n; ++c)
+        for (int r = L0.h_cp[cells[c]]; r < L0.h_cp[cells[c] + 1]; ++r)
+            for (int b = L0.h_rp[r]; b < L0.h_rp[r + 1]; ++b)
+                for (int e : {b, L0.h_btr[b]})
+                    if (!L0.h_bmark[e]) {
+                        L0.h_bmark[e] = 1;
+                        cur.push_back(e);
+                    }
+    for (int t = 0; t < nl; ++t) {
+        Level& lv = h->L[t];
+        boff[t] = used;
+        bcnt[t] = (int64_t)cur.size();
+        for (int b : cur) stage[used++] = b;
+        coff[t] = used;
+        ccnt[t] = 0;
+        if (t + 1 < nl) {
+            for (int b : cur) {
+                const int c = lv.h_cor[lv.h_rob[b]];
+                if (c == lv.h_cor[lv.h_ci[b]] && !lv.h_cmark[c]) {
+                    lv.h_cmark[c] = 1;
+                    stage[used++] = c;
+                    ccnt[t]++;
+                }
+            }
+            for (int64_t k = 0; k < ccnt[t]; ++k) lv.h_cmark[stage[coff[t] + k]] = 0;
+            Level& cl = h->L[t + 1];
+            nxt.clear();
+            for (int b : cur) {
+                const int cb = lv.t_kind == XDG_T_PTRUNC ? b : lv.h_fb2cb[b];
+                if (!cl.h_bmark[cb]) {
+                    cl.h_bmark[cb] = 1;
+                    nxt.push_back(cb);
+                }
+            }
+        }
+        for (int b : cur) lv.h_bmark[b] = 0;
+        cur.swap(nxt);
+    }
+    hipStream_t s = h->s;
+    HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), s));
+    if (used > 0)
+        HIPCHK(hipMemcpyAsync(h->d_stage, stage, used * sizeof(int), hipMemcpyHostToDevice, s));
+    for (int t = 0; t < nl; ++t) {
+        Level& lv = h->L[t];
+        const int* bl = h->d_stage + boff[t];
+        if (t == 0) {
+            launch_transpose_list(s, (int)bcnt[t], bl, lv.np, val_dev, lv.A64);
+        } else {
+            Level& f = h->L[t - 1];
+            if (f.t_kind == XDG_T_PTRUNC)
+                launch_extract_list(s, (int)bcnt[t], bl, f.np, lv.np, f.A64, lv.A64);
+            else
+                launch_galerkin_dense(s, (int)bcnt[t], f.np, lv.np, f.g_ptr, f.g_fb, f.g_row,
+                                      f.g_col, f.A64, f.R64, lv.A64, bl);
+        }
+        if (t + 1 < nl && ccnt[t] > 0) {
+            const int* cl = h->d_stage + coff[t];
+            launch_gather_cells(s, (int)ccnt[t], lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff,
+                                lv.D64, cl);
+            launch_gj_batched(s, (int)ccnt[t], lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64, h->d_err,
+                              cl);
+        }
+    }
+    CHK(invert_coarsest(h, h->L[nl - 1]));
+    if (h->mixed) {
+        for (int l = 0; l + 1 < nl; ++l) {
+            Level& lv = h->L[l];
+            launch_convert<double, float>(s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
+            launch_convert<double, float>(s, lv.dsize, lv.D64, lv.D32);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return check_setup_error(h);   // synchronises: the stage may be reused afterwards
 }
 
 extern "C" int xdg_set_tolerance(xdg_handle* h, double rtol, int32_t maxit) {

@@ -45,6 +45,11 @@ struct Level {
     float* D32 = nullptr;
     // Galerkin contributions forming the next coarser level (dense transfers)
     int *g_ptr = nullptr, *g_fb = nullptr, *g_row = nullptr, *g_col = nullptr;
+    std::vector<int> h_fb2cb;       // fine block -> the coarse block it contributes to
+    // partial update (built on first use): row of every block, cell of every
+    // row, level 0: index of the transposed block (l, i) of block (i, l)
+    std::vector<int> h_rob, h_cor, h_btr;
+    std::vector<char> h_bmark, h_cmark;
     // transfer to the next coarser level
     int t_kind = -1, npc = 0, n_c = 0;
     int *parent = nullptr, *chp = nullptr, *chi = nullptr;
@@ -93,6 +98,8 @@ struct xdg_handle {
     std::vector<Level> L;
     int cn = 0, cld = 0;            // coarsest order, padded leading dimension
     double* Cinv = nullptr;
+    int *h_stage = nullptr, *d_stage = nullptr;   // pinned / device lists of a partial update
+    int64_t stage_len = 0;
     double* Pbuf = nullptr;         // pivot-tile inverses of the coarse inversion (two panels)
     double* scal = nullptr;         // device scalars
     double* part = nullptr;         // reduction partials

@@ -47,14 +47,20 @@ template <typename T>
 void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* in, T* out);
 void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const double* A,
                             double* Ac);
+// list == nullptr: every coarse block / cell 0..n-1; else the n listed ones
 void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
                            const int* cfb, const int* ci_row, const int* ci_col,
-                           const double* A, const double* R, double* Ac);
+                           const double* A, const double* R, double* Ac, const int* list);
 void launch_gather_cells(hipStream_t s, int n_cells, int np, const int* cell_ptr,
                          const int* rp, const int* ci, const double* A, const int64_t* doff,
-                         double* D);
+                         double* D, const int* list);
 void launch_gj_batched(hipStream_t s, int n_mats, const int64_t* doff, const int* cell_ptr,
-                       int np, int max_n, double* D, int* err);
+                       int np, int max_n, double* D, int* err, const int* list);
+// row-major -> column-major layout and leading-mode extraction of listed blocks
+void launch_transpose_list(hipStream_t s, int n, const int* list, int np, const double* in,
+                           double* out);
+void launch_extract_list(hipStream_t s, int n, const int* list, int npf, int npc,
+                         const double* A, double* Ac);
 void launch_bsr_to_dense(hipStream_t s, int n_rows, int np, const int* rp, const int* ci,
                          const double* A, int ld, int npad, double* dense);
 void launch_coarse_gj_step(hipStream_t s, int nt, int K, int ld, double* A, double* P,

@@ -88,6 +88,7 @@ def test_null_handle_calls_fail_cleanly():
     import ctypes as C
     assert B.lib().xdg_level_info(None, 0, None, None, None) == B.XDG_EINVAL
     assert B.lib().xdg_vcycle(None, None, None) == B.XDG_EINVAL
+    assert B.lib().xdg_update_cells(None, None, 1, None) == B.XDG_EINVAL
     assert "NULL" in B.xdg_last_error() or "handle" in B.xdg_last_error()
     B.lib().xdg_destroy(None)
 

@@ -376,6 +376,56 @@ def test_update_matrix_and_errors(torch):
     assert e.value.code == B.XDG_ENOTSPD
 
 
+@pytest.mark.parametrize("name", ["c2n8", "c2n16", "c4n8p4"])
+def test_update_cells_equals_full_update(name, torch):
+    """New values with the rows and columns of a set of cells scaled (the cut
+    cells carrying both species, S M S with S = 1.25 there, still SPD): the
+    partial update of those cells gives the hierarchy, every cell inverse,
+    the coarsest inverse and the solve of the full update bit for bit, and
+    differs from the hierarchy before the update."""
+    from paper_2003_02431_amd import binding as B
+    pr, H, S0 = _case(name, torch)
+    cp = np.asarray(pr.cell_ptr)
+    cells = np.flatnonzero(np.diff(cp) == 2)
+    if cells.size == 0:
+        cells = np.arange(0, len(cp) - 1, 7)
+    scale = np.ones(pr.n_rows)
+    for c in cells:
+        scale[cp[c]:cp[c + 1]] = 1.25
+    row_of = np.repeat(np.arange(pr.n_rows), np.diff(pr.row_ptr))
+    val2 = pr.val * (scale[row_of] * scale[pr.col_idx])[:, None, None]
+    v2 = torch.as_tensor(np.ascontiguousarray(val2)).cuda()
+    opt = B.options(rtol=1e-10, maxit=600)
+    Sf, Sp = B.Solver(pr, opt), B.Solver(pr, opt)
+    B.xdg_update_matrix(Sf.h, v2)
+    B.xdg_update_cells(Sp.h, v2, cells)
+    nlev = H.nlev
+    for l in range(nlev):
+        a, b = B.xdg_get_level_matrix(Sf.h, l), B.xdg_get_level_matrix(Sp.h, l)
+        assert all(np.array_equal(u, w) for u, w in zip(a, b)), f"level {l}"
+    a0 = B.xdg_get_level_matrix(S0.h, 1)[2]
+    assert not np.array_equal(a0, B.xdg_get_level_matrix(Sp.h, 1)[2])
+    for l in range(nlev - 1):
+        n_cells = len(H.cell_ptr[l]) - 1
+        for c in range(n_cells):
+            assert np.array_equal(B.xdg_get_cell_inverse(Sf.h, l, c),
+                                  B.xdg_get_cell_inverse(Sp.h, l, c)), f"level {l} cell {c}"
+    assert np.array_equal(B.xdg_get_cell_inverse(Sf.h, nlev - 1, 0),
+                          B.xdg_get_cell_inverse(Sp.h, nlev - 1, 0))
+    b = Sf.vec(0, pr.b)
+    xf, xp = Sf.vec(0), Sp.vec(0)
+    rf = B.xdg_solve(Sf.h, b, xf)
+    rp = B.xdg_solve(Sp.h, b, xp)
+    _log(f"  {name}: {cells.size} cells updated, solve it {rf[1]} / {rp[1]}")
+    assert rf[0] == 0 and rp[0] == 0 and torch.equal(xf, xp)
+    with pytest.raises(B.XdgError):
+        B.xdg_update_cells(Sp.h, v2, [int(cells[0]), int(cells[0])])
+    with pytest.raises(B.XdgError):
+        B.xdg_update_cells(Sp.h, v2, [len(cp) - 1])
+    Sf.close()
+    Sp.close()
+
+
 def test_full_size_sampled(torch):
     """The 32^3 p=3 workload in the launch configuration the benchmark uses:
     sampled SpMV rows against the oracle, every Galerkin level in full, and
