@@ -373,6 +373,64 @@ __global__ __launch_bounds__(256) void k_cgj_col(int nt, int K, int ld, double* 
     }
 }
 
+// column K (with P = inverse of panel K's pivot) and row K+1 (with Pn, the
+// next pivot inverse) in one launch: groups 0..nt-1 do column K except tile
+// (K+1, K); groups nt.. do row K+1, and the group of tile (K+1, K) first
+// applies the column-K step to it, then the row-(K+1) step -- the order of
+// separate launches.  The two steps touch no other common tile.
+__global__ __launch_bounds__(256) void k_cgj_colrow(int nt, int K, int ld, double* __restrict__ A,
+                                                    const double* __restrict__ P,
+                                                    const double* __restrict__ Pn) {
+    __shared__ double p[NB][NB + 1], t[NB][NB + 1];
+    const int w = blockIdx.x;
+    if (w < nt) {                              // column K
+        const int I = w;
+        if (I == K + 1) return;
+        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = P[e];
+        if (I == K) {
+            for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
+                A[(int64_t)(K * NB + e / NB) * ld + K * NB + e % NB] = P[e];
+            return;
+        }
+        load_tile(t, A, ld, I, K);
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+            const int r = e / NB, c = e - r * NB;
+            double sum = 0.0;
+            for (int k = 0; k < NB; ++k) sum += t[r][k] * p[k][c];
+            A[(int64_t)(I * NB + r) * ld + K * NB + c] = -sum;
+        }
+        return;
+    }
+    const int jj = w - nt;                     // row K+1, J != K+1
+    const int J = jj + (jj >= K + 1 ? 1 : 0);
+    load_tile(t, A, ld, K + 1, J);
+    if (J == K) {                              // column-K step on tile (K+1, K) first
+        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = P[e];
+        __syncthreads();
+        double v[4];
+        int q = 0;
+        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x, ++q) {
+            const int r = e / NB, c = e - r * NB;
+            double sum = 0.0;
+            for (int k = 0; k < NB; ++k) sum += t[r][k] * p[k][c];
+            v[q] = -sum;
+        }
+        __syncthreads();
+        q = 0;
+        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x, ++q) t[e / NB][e % NB] = v[q];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = Pn[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int r = e / NB, c = e - r * NB;
+        double sum = 0.0;
+        for (int k = 0; k < NB; ++k) sum += p[r][k] * t[k][c];
+        A[(int64_t)((K + 1) * NB + r) * ld + J * NB + c] = sum;
+    }
+}
+
 template <typename Tin, typename Tout>
 __global__ void k_convert(int64_t n, const Tin* __restrict__ in, Tout* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -423,15 +481,19 @@ void launch_bsr_to_dense(hipStream_t s, int n_rows, int np, const int* rp, const
 }
 void launch_coarse_gj_step(hipStream_t s, int nt, int K, int ld, double* A, double* P2, int* err) {
     // P2 holds two pivot inverses: panel K uses P2[K % 2]; the update of
-    // panel K writes the inverse for panel K + 1 into the other half
+    // panel K writes the inverse for panel K + 1 into the other half, and the
+    // row step of panel K + 1 runs together with the column step of panel K
     double* P = P2 + (K & 1) * NB * NB;
     double* Pn = P2 + ((K + 1) & 1) * NB * NB;
-    if (K == 0) k_cgj_pivot<<<1, 256, 0, s>>>(K, ld, A, P, err);
-    if (nt > 1) {
-        k_cgj_row<<<nt - 1, 256, 0, s>>>(nt, K, ld, A, P);
-        k_cgj_update<<<(nt - 1) * (nt - 1), 256, 0, s>>>(nt, K, ld, A, Pn, err);
+    if (K == 0) {
+        k_cgj_pivot<<<1, 256, 0, s>>>(K, ld, A, P, err);
+        if (nt > 1) k_cgj_row<<<nt - 1, 256, 0, s>>>(nt, K, ld, A, P);
     }
-    k_cgj_col<<<nt, 256, 0, s>>>(nt, K, ld, A, P);
+    if (nt > 1) k_cgj_update<<<(nt - 1) * (nt - 1), 256, 0, s>>>(nt, K, ld, A, Pn, err);
+    if (K + 1 < nt)
+        k_cgj_colrow<<<2 * nt - 1, 256, 0, s>>>(nt, K, ld, A, P, Pn);
+    else
+        k_cgj_col<<<nt, 256, 0, s>>>(nt, K, ld, A, P);
 }
 template <typename Tin, typename Tout>
 void launch_convert(hipStream_t s, int64_t n, const Tin* in, Tout* out) {
