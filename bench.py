@@ -350,7 +350,7 @@ def main():
                     help="only launch the level-0 SpMV 20 times and a plain copy (counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
+        print("bench.py: the solver runs on exactly one GPU (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
