@@ -179,8 +179,9 @@ int xdg_update_matrix(xdg_handle *h, const double *val_dev);
  * are recomputed on every level; the coarsest inverse is rebuilt.  When the
  * values outside those rows and columns are unchanged the result equals
  * xdg_update_matrix's bit for bit.  cells_host: n >= 1 distinct indices in
- * [0, n_cells).  Single-column handles (nrhs = 1).  Synchronises the stream;
- * XDG_ENOTSPD on a non-positive pivot. */
+ * [0, n_cells).  Single-column handles (nrhs = 1); the level-0 block pattern
+ * must be symmetric (checked on the first call, XDG_EINVAL otherwise).
+ * Synchronises the stream; XDG_ENOTSPD on a non-positive pivot. */
 int xdg_update_cells(xdg_handle *h, const double *val_dev, int32_t n,
                      const int32_t *cells_host);
 
