@@ -104,26 +104,59 @@ typedef struct {
 int xdg_create(const xdg_matrix *A0, int32_t n_levels, const xdg_transfer *T,
                const xdg_options *opt, void *hip_stream, xdg_handle **out);
 
-/* y = M^lambda x on level `level` (Eq. GenericMatrixSystem). */
+/* y = M^lambda x on level `level`: the operator of the level's system
+ * (Eq. GenericMatrixSystem on level 0, the Galerkin matrix of Eq.
+ * XDGsysRestriction below it), one dense Np x Np block per stored
+ * (row, column) pair.  x_dev, y_dev: n_rows * np doubles of that level
+ * (caller-owned, device).  A 16-column handle computes the FP64
+ * matrix-core product of level 0 on [row][mode][16] vectors and returns
+ * XDG_EINVAL for level > 0 (xdg_spmm with XDG_MIXED covers those). */
 int xdg_spmv(xdg_handle *h, int32_t level, const double *x_dev, double *y_dev);
 
 /* `sweeps` damped block-Jacobi sweeps x <- x + omega D^{-1} (b - M x) on
- * `level`, D the cell-block diagonal; x is updated in place. */
+ * `level` (level < n_levels - 1), D the cell-block diagonal.  The blocks are
+ * the per-cell dense solves of Section 3.3 (Algorithm pMultigrid solves the
+ * system restricted to the modes m(j,-,-,.) of one cell j directly), taken
+ * over all modes and all species of a cell and applied to every cell at once
+ * with damping omega.  b_dev is read, x_dev updated in place (both n_rows * np
+ * doubles of the level, times 16 on a 16-column handle, which sweeps in FP32
+ * on the matrix cores).  sweeps >= 0. */
 int xdg_smooth(xdg_handle *h, int32_t level, const double *b_dev, double *x_dev,
                int32_t sweeps);
 
-/* rc = (R^{X,level})^T rf : fine level `level` -> level+1. */
+/* rc = (R^{X,level})^T rf : fine level `level` -> level+1, with R^{X,level}
+ * the prolongation matrix of Eq. XDGrestrictionMatrix (per fine block row
+ * the projection of the fine basis onto the coarse one; on a p-level the
+ * leading coarse modes, Section 3.2) and its transpose the restriction of
+ * Eq. XDGsysRestriction.  rf_dev: fine level vector, rc_dev: coarse level
+ * vector (overwritten); [row][mode][16] on a 16-column handle (FP64). */
 int xdg_restrict(xdg_handle *h, int32_t level, const double *rf_dev, double *rc_dev);
 
-/* xf += R^{X,level} xc : level+1 -> fine level `level`. */
+/* xf += R^{X,level} xc : level+1 -> fine level `level` (Eq.
+ * XDGrestrictionMatrix); xf_dev is accumulated into, xc_dev read;
+ * [row][mode][16] on a 16-column handle (FP64). */
 int xdg_prolong(xdg_handle *h, int32_t level, const double *xc_dev, double *xf_dev);
 
-/* z = B r, one symmetric V-cycle from level 0 (pre-smoothing from zero,
- * coarse-grid correction, post-smoothing, exact coarsest solve). */
+/* z = B r, one symmetric V-cycle from level 0: on every level nu_pre damped
+ * block-Jacobi sweeps from zero, residual, restriction, the cycle of the
+ * level below, prolongation-add, nu_post sweeps; the coarsest level is
+ * solved exactly (its explicit FP64 inverse).  This is the classical cycle
+ * of multigrid textbooks over the hierarchy of Section 3.1 (Eq.
+ * MultigridAggMeshSeq, Galerkin levels of Eq. XDGsysRestriction); Section
+ * 3.3 warns that this cycle can diverge for (X)DG systems, which the
+ * orthonormalisation multigrid of Algorithm OrthoMG (krylov XDG_ORTHOMG)
+ * guards against.  Pre and post smoothing are alike, so B is symmetric and
+ * serves as the CG preconditioner.  r_dev read, z_dev overwritten
+ * (level-0 vectors; 16 columns on a 16-column handle). */
 int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
 
-/* Solves M^0 x = b.  x_dev holds the initial guess on entry and the solution
- * on return.  hist_host[k] = ||r_k||_2/||b||_2, k = 0..*iters (at most
+/* Solves M^0 x = b (Eq. GenericMatrixSystem on level 0) with the V-cycle
+ * above as preconditioner of CG (XDG_CG; flexible CG with XDG_MIXED) or of
+ * flexible GMRES(restart) with FP64 restarts (XDG_FGMRES), until the
+ * residual criterion of Section 4, read relative:
+ * ||b - M x||_2 / ||b||_2 <= rtol on the coefficient vectors (the paper
+ * stops at an absolute 2-norm of 1e-10).  x_dev holds the initial guess on
+ * entry and the solution on return.  hist_host[k] = ||r_k||_2/||b||_2, k = 0..*iters (at most
  * hist_cap entries are written); *final_relres is the recomputed true FP64
  * residual.  Returns XDG_ENOCONV (x valid) when maxit is reached.
  * krylov = XDG_ORTHOMG solves with the orthonormalisation multigrid of

@@ -137,6 +137,33 @@ def _np(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
+# columns per vector and level-0 smoother cells of every live handle (keyed by
+# the handle's address): the device-vector length checks below need them
+_HANDLES = {}
+
+
+def _key(h):
+    return h.value if isinstance(h, C.c_void_p) else int(h)
+
+
+def _need(t, n, what):
+    """Refuse a device buffer shorter than the n elements the call touches
+    (the library only sees a pointer and would read or write past its end)."""
+    if t.numel() < n:
+        raise ValueError(f"{what}: device buffer holds {t.numel()} elements, the call needs {n}")
+
+
+def _vlen(h, level):
+    n, npm, _ = xdg_level_info(h, level)
+    return n * npm * _HANDLES.get(_key(h), (1, 0))[0]
+
+
+def _vec(h, level, t, what):
+    p = _ptr(t)
+    _need(t, _vlen(h, level), what)
+    return p
+
+
 def options(krylov=XDG_CG, restart=30, maxit=500, nu_pre=2, nu_post=2, precision=XDG_FP64,
             smoother=XDG_JACOBI, nrhs=1, rtol=1e-10, omega=0.7):
     return xdg_options(krylov, restart, maxit, nu_pre, nu_post, precision, smoother, nrhs,
@@ -169,27 +196,31 @@ def xdg_create(row_ptr, col_idx, val, cell_ptr, transfers, opt, stream=None):
     h = C.c_void_p()
     _check(_lib.xdg_create(C.byref(m), len(transfers) + 1, T, C.byref(opt),
                            C.c_void_p(stream or 0), C.byref(h)))
+    _HANDLES[_key(h)] = (int(opt.nrhs), len(cp) - 1)
     return h
 
 
 def xdg_spmv(h, level, x, y):
-    return _check(_lib.xdg_spmv(h, level, _ptr(x), _ptr(y)))
+    return _check(_lib.xdg_spmv(h, level, _vec(h, level, x, "x"), _vec(h, level, y, "y")))
 
 
 def xdg_smooth(h, level, b, x, sweeps):
-    return _check(_lib.xdg_smooth(h, level, _ptr(b), _ptr(x), sweeps))
+    return _check(_lib.xdg_smooth(h, level, _vec(h, level, b, "b"), _vec(h, level, x, "x"),
+                                  sweeps))
 
 
 def xdg_restrict(h, level, rf, rc):
-    return _check(_lib.xdg_restrict(h, level, _ptr(rf), _ptr(rc)))
+    return _check(_lib.xdg_restrict(h, level, _vec(h, level, rf, "rf"),
+                                    _vec(h, level + 1, rc, "rc")))
 
 
 def xdg_prolong(h, level, xc, xf):
-    return _check(_lib.xdg_prolong(h, level, _ptr(xc), _ptr(xf)))
+    return _check(_lib.xdg_prolong(h, level, _vec(h, level + 1, xc, "xc"),
+                                   _vec(h, level, xf, "xf")))
 
 
 def xdg_vcycle(h, r, z):
-    return _check(_lib.xdg_vcycle(h, _ptr(r), _ptr(z)))
+    return _check(_lib.xdg_vcycle(h, _vec(h, 0, r, "r"), _vec(h, 0, z, "z")))
 
 
 def xdg_solve(h, b, x, hist_cap=1000):
@@ -197,7 +228,8 @@ def xdg_solve(h, b, x, hist_cap=1000):
     hist = np.zeros(hist_cap)
     it = C.c_int32()
     fr = C.c_double()
-    rc = _check(_lib.xdg_solve(h, _ptr(b), _ptr(x), hist.ctypes.data_as(_f64p), hist_cap,
+    rc = _check(_lib.xdg_solve(h, _vec(h, 0, b, "b"), _vec(h, 0, x, "x"),
+                               hist.ctypes.data_as(_f64p), hist_cap,
                                C.byref(it), C.byref(fr)))
     return rc, it.value, fr.value, hist[:min(it.value + 1, hist_cap)].copy()
 
@@ -227,17 +259,25 @@ def xdg_get_cell_inverse(h, level, cell, cap=1 << 24):
 
 
 def xdg_spmm(h, level, precision, X, Y):
-    return _check(_lib.xdg_spmm(h, level, precision, _ptr(X), _ptr(Y)))
+    return _check(_lib.xdg_spmm(h, level, precision, _vec(h, level, X, "X"),
+                                _vec(h, level, Y, "Y")))
+
+
+def _vals(h, val_dev):
+    p = _ptr(val_dev)
+    _, npm, nnzb = xdg_level_info(h, 0)
+    _need(val_dev, nnzb * npm * npm, "val_dev")
+    return p
 
 
 def xdg_update_matrix(h, val_dev):
-    return _check(_lib.xdg_update_matrix(h, _ptr(val_dev)))
+    return _check(_lib.xdg_update_matrix(h, _vals(h, val_dev)))
 
 
 def xdg_update_cells(h, val_dev, cells):
     """New level-0 values changed only in the rows/columns of `cells`."""
     c = np.ascontiguousarray(cells, dtype=np.int32)
-    return _check(_lib.xdg_update_cells(h, _ptr(val_dev), int(c.size),
+    return _check(_lib.xdg_update_cells(h, _vals(h, val_dev), int(c.size),
                                         c.ctypes.data_as(_i32p)))
 
 
@@ -264,14 +304,24 @@ def xdg_mlp_get(h):
     return p
 
 
+def _samples(X, T, n_in=45, n_out=40):
+    n = X.shape[0]
+    _need(X, n * n_in, "X")
+    _need(T, n * n_out, "T")
+    return n
+
+
 def xdg_mlp_forward(h, X, Y):
-    return _check(_lib.xdg_mlp_forward(h, X.shape[0], _ptr32(X), _ptr32(Y)))
+    n = _samples(X, Y)
+    return _check(_lib.xdg_mlp_forward(h, n, _ptr32(X), _ptr32(Y)))
 
 
 def xdg_mlp_gradient(h, X, T, grad):
     """Fills grad (float32 device tensor) and returns the loss."""
     loss = C.c_float()
-    _check(_lib.xdg_mlp_gradient(h, X.shape[0], _ptr32(X), _ptr32(T), _ptr32(grad),
+    n = _samples(X, T)
+    _need(grad, xdg_mlp_param_count(), "grad")
+    _check(_lib.xdg_mlp_gradient(h, n, _ptr32(X), _ptr32(T), _ptr32(grad),
                                  C.byref(loss)))
     return loss.value
 
@@ -279,7 +329,8 @@ def xdg_mlp_gradient(h, X, T, grad):
 def xdg_mlp_train(h, X, T, batch, steps, lr):
     """Returns the minibatch loss history (numpy float32, one per step)."""
     hist = np.zeros(max(steps, 1), np.float32)
-    _check(_lib.xdg_mlp_train(h, X.shape[0], _ptr32(X), _ptr32(T), batch, steps, lr,
+    n = _samples(X, T)
+    _check(_lib.xdg_mlp_train(h, n, _ptr32(X), _ptr32(T), batch, steps, lr,
                               hist.ctypes.data_as(_f32p)))
     return hist[:steps]
 
@@ -294,7 +345,13 @@ def xdg_set_cell_features(h, row_species, cell_geom):
 def xdg_learned_pairs(h, b, xk, xs, cell0, cell_step, X, T, clip=0.0):
     """Writes the pairs into X, T (float32 device tensors); returns the count."""
     n = C.c_int32()
-    _check(_lib.xdg_learned_pairs(h, _ptr(b), _ptr(xk), _ptr(xs), cell0, cell_step, clip,
+    n_cells = _HANDLES.get(_key(h), (1, 0))[1]
+    if cell_step >= 1 and 0 <= cell0 < n_cells:
+        m = (n_cells - cell0 + cell_step - 1) // cell_step
+        _need(X, m * 45, "X")
+        _need(T, m * 40, "T")
+    _check(_lib.xdg_learned_pairs(h, _vec(h, 0, b, "b"), _vec(h, 0, xk, "xk"),
+                                  _vec(h, 0, xs, "xs"), cell0, cell_step, clip,
                                   _ptr32(X), _ptr32(T), C.byref(n)))
     return n.value
 
@@ -314,6 +371,7 @@ def xdg_learned_stats(h):
 
 
 def xdg_destroy(h):
+    _HANDLES.pop(_key(h), None)
     _lib.xdg_destroy(h)
 
 

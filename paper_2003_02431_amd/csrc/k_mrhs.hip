@@ -306,6 +306,17 @@ __global__ void k_prolong_trunc_m(int n_rows, int npf, int npc, const T* __restr
     xf[i * npf * 16 + rem] += xc[t];
 }
 
+// rc[i][m][k] = rf[i][m][k] for the leading npc modes (p-truncation)
+template <typename T>
+__global__ void k_restrict_trunc_m(int n_rows, int npf, int npc, const T* __restrict__ rf,
+                                   T* __restrict__ rc) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_rows * npc * 16) return;
+    const int64_t i = t / (npc * 16);
+    const int rem = (int)(t - i * npc * 16);
+    rc[t] = rf[i * npf * 16 + rem];
+}
+
 // rc[c][m][k] = sum_{i in children(c)} sum_a R_i[a][m] rf[i][a][k]
 template <typename T>
 __global__ void k_restrict_dense_m(int n_c, int npf, int npc, const int* __restrict__ child_ptr,
@@ -425,6 +436,10 @@ void launch_prolong_trunc_m(hipStream_t s, int n_rows, int npf, int npc, const T
     k_prolong_trunc_m<T><<<nb_((int64_t)n_rows * npc * 16, 256), 256, 0, s>>>(n_rows, npf, npc, xc, xf);
 }
 template <typename T>
+void launch_restrict_trunc_m(hipStream_t s, int n_rows, int npf, int npc, const T* rf, T* rc) {
+    k_restrict_trunc_m<T><<<nb_((int64_t)n_rows * npc * 16, 256), 256, 0, s>>>(n_rows, npf, npc, rf, rc);
+}
+template <typename T>
 void launch_restrict_dense_m(hipStream_t s, int n_c, int npf, int npc, const int* cptr,
                              const int* cidx, const T* R, const T* rf, T* rc) {
     k_restrict_dense_m<T><<<nb_((int64_t)n_c * npc * 16, 256), 256, 0, s>>>(n_c, npf, npc, cptr,
@@ -456,6 +471,13 @@ template void launch_restrict_dense_m<float>(hipStream_t, int, int, int, const i
                                              const float*, const float*, float*);
 template void launch_prolong_dense_m<float>(hipStream_t, int, int, int, const int*, const float*,
                                             const float*, float*);
+// FP64 forms: the boundary's restriction / prolongation on 16-column vectors
+template void launch_restrict_trunc_m<double>(hipStream_t, int, int, int, const double*, double*);
+template void launch_prolong_trunc_m<double>(hipStream_t, int, int, int, const double*, double*);
+template void launch_restrict_dense_m<double>(hipStream_t, int, int, int, const int*, const int*,
+                                              const double*, const double*, double*);
+template void launch_prolong_dense_m<double>(hipStream_t, int, int, int, const int*,
+                                             const double*, const double*, double*);
 
 }  // namespace xdg
 

@@ -531,6 +531,14 @@ extern "C" int xdg_spmv(xdg_handle* h, int32_t level, const double* x, double* y
     CHK(check_level(h, level, false));
     if (!x || !y) return fail(XDG_EINVAL, "xdg_spmv: NULL vector");
     Level& lv = h->L[level];
+    if (h->nrhs == kNrhs) {
+        // 16 columns [row][mode][16]: the FP64 matrix-core product of level 0
+        // (the only level with packed FP64 blocks)
+        if (level != 0)
+            return fail(XDG_EINVAL, "xdg_spmv: a 16-column handle has the FP64 product on "
+                                    "level 0 only (xdg_spmm with XDG_MIXED for coarser levels)");
+        return mrhs_spmm(h, 0, XDG_FP64, x, y);
+    }
     launch_spmv<double>(h->s, SPMV_AX, lv.n_rows, lv.np, lv.rp, lv.ci, lv.A64, x, nullptr, y, 0);
     HIPCHK(hipGetLastError());
     return XDG_OK;
@@ -557,7 +565,13 @@ extern "C" int xdg_restrict(xdg_handle* h, int32_t level, const double* rf, doub
     if (!rf || !rc) return fail(XDG_EINVAL, "xdg_restrict: NULL vector");
     Level& f = h->L[level];
     Level& c = h->L[level + 1];
-    if (f.t_kind == XDG_T_PTRUNC)
+    if (h->nrhs == kNrhs) {
+        if (f.t_kind == XDG_T_PTRUNC)
+            launch_restrict_trunc_m<double>(h->s, f.n_rows, f.np, c.np, rf, rc);
+        else
+            launch_restrict_dense_m<double>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.R64, rf,
+                                            rc);
+    } else if (f.t_kind == XDG_T_PTRUNC)
         launch_restrict_trunc<double>(h->s, f.n_rows, f.np, c.np, rf, rc);
     else
         launch_restrict_dense<double>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.R64, rf, rc);
@@ -570,7 +584,12 @@ extern "C" int xdg_prolong(xdg_handle* h, int32_t level, const double* xc, doubl
     if (!xc || !xf) return fail(XDG_EINVAL, "xdg_prolong: NULL vector");
     Level& f = h->L[level];
     Level& c = h->L[level + 1];
-    if (f.t_kind == XDG_T_PTRUNC)
+    if (h->nrhs == kNrhs) {
+        if (f.t_kind == XDG_T_PTRUNC)
+            launch_prolong_trunc_m<double>(h->s, f.n_rows, f.np, c.np, xc, xf);
+        else
+            launch_prolong_dense_m<double>(h->s, f.n_rows, f.np, c.np, f.parent, f.R64, xc, xf);
+    } else if (f.t_kind == XDG_T_PTRUNC)
         launch_prolong_trunc<double>(h->s, f.n_rows, f.np, c.np, xc, xf);
     else
         launch_prolong_dense<double>(h->s, f.n_rows, f.np, c.np, f.parent, f.R64, xc, xf);

@@ -119,6 +119,8 @@ void launch_pack_blocks(hipStream_t s, int64_t nblocks, int n, const double* in,
 void launch_pack_cells(hipStream_t s, int n_cells, int np, const int* cp, const int64_t* doff,
                        const double* in, float* out);
 template <typename T>
+void launch_restrict_trunc_m(hipStream_t s, int n_rows, int npf, int npc, const T* rf, T* rc);
+template <typename T>
 void launch_prolong_trunc_m(hipStream_t s, int n_rows, int npf, int npc, const T* xc, T* xf);
 template <typename T>
 void launch_restrict_dense_m(hipStream_t s, int n_c, int npf, int npc, const int* cptr,

@@ -148,8 +148,51 @@ def test_smoother(name, torch):
         assert ratio <= 1.0 and e <= 1e-2
 
 
+def _fp32_cycle(H, ops, r, level=0):
+    """The V-cycle of the oracle evaluated in FP32 arithmetic on the CPU: the
+    oracle's own damped-Jacobi and transfer steps on FP32 operators and FP32
+    vectors (every sparse product accumulates in FP32, in the order the
+    operator's rows store their entries), the coarsest level solved in FP64
+    from the FP32 residual and rounded back, as the device does."""
+    from oracle import mg
+    if level == H.nlev - 1:
+        return H.coarse_solve(r.astype(np.float64)).astype(np.float32)
+    A, D, Rt, R = ops[level]
+    om = np.float32(0.7)
+    x = mg.jacobi(A, D, r, np.zeros_like(r), om, H.nu_pre)
+    rc = Rt @ (r - A @ x)
+    x = x + R @ _fp32_cycle(H, ops, rc, level + 1)
+    return mg.jacobi(A, D, r, x, om, H.nu_post)
+
+
+def _csr32(M, reverse=False):
+    """M as FP32 CSR; reverse: every row's entries stored in reverse order
+    (a second summation order for the same products)."""
+    import scipy.sparse as sp
+    M = M.tocsr().astype(np.float32)
+    M.sort_indices()
+    if not reverse:
+        return M
+    ip, ix, d = M.indptr, M.indices.copy(), M.data.copy()
+    for i in range(M.shape[0]):
+        ix[ip[i]:ip[i + 1]] = ix[ip[i]:ip[i + 1]][::-1]
+        d[ip[i]:ip[i + 1]] = d[ip[i]:ip[i + 1]][::-1]
+    N = sp.csr_matrix((d, ix, ip), shape=M.shape)
+    N.has_sorted_indices = False
+    return N
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_vcycle(name, torch):
+    """The FP32 MFMA V-cycle against the cycle in exact arithmetic on the
+    FP32-rounded operators (the reference).  How far FP32 arithmetic may move
+    the cycle is measured, not guessed: the same cycle is evaluated in FP32 on
+    the CPU in two summation orders (row entries forward, and reversed); the
+    device's distance from the reference must not exceed 4 times the larger
+    of theirs.  The cycle's rounding sensitivity is large (cell blocks with
+    kappa up to ~1e6 at mu 1:1000: 3e-5..1e-4 relative), so a fixed FP32
+    tolerance would be either loose or wrong, and a componentwise a priori
+    bound through |D^-1| |M| grows by orders of magnitude per sweep."""
     from oracle import mg
     from paper_2003_02431_amd import binding as B
     pr, H, S = _case(name, torch)
@@ -158,19 +201,107 @@ def test_vcycle(name, torch):
     z = S.vec(0)
     B.xdg_vcycle(S.h, S.vec(0, r), z)
     zg = _cols(z.cpu().numpy(), L)
-    # oracle with every level operator, inverse and transfer rounded to FP32
+    r32 = r.astype(np.float32)
+    # reference: every level operator, inverse and transfer rounded to FP32,
+    # exact (FP64) arithmetic, the device's FP32 omega
     H32 = mg.hierarchy_of(pr)
     H32.A = [_f32(A) for A in H.A[:-1]] + [H.A[-1]]
     H32.Dinv = [_f32(D) for D in H.Dinv]
     H32.R = [_f32(R) for R in H.R]
-    ref32 = np.column_stack([H32.vcycle(r[:, c].astype(np.float32).astype(np.float64))
-                             for c in range(K)])
+    H32.omega = float(np.float32(0.7))
+    ref32 = np.column_stack([H32.vcycle(r32[:, c].astype(np.float64)) for c in range(K)])
+    spread = 0.0
+    for rev in (False, True):
+        ops = [(_csr32(H.A[l], rev), _csr32(H.Dinv[l], rev), _csr32(H.R[l].T, rev),
+                _csr32(H.R[l], rev)) for l in range(H.nlev - 1)]
+        ze = _fp32_cycle(H, ops, r32).astype(np.float64)
+        spread = max(spread, _rel(ze, ref32))
     ref = np.column_stack([H.vcycle(r[:, c]) for c in range(K)])
     e32, e = _rel(zg, ref32), _rel(zg, ref)
-    _log(f"  {name}: MFMA V-cycle rel err {e:.2e} (vs rounded operators {e32:.2e})")
-    # the FP32 cycle is a preconditioner: its accuracy is pinned through the
-    # kernels above and through the solve below; this only guards gross errors
-    assert e32 <= 1e-2 and e <= 1e-2
+    _log(f"  {name}: MFMA V-cycle rel err {e:.2e}; vs the rounded operators {e32:.2e}, "
+         f"FP32 evaluations on the CPU {spread:.2e}")
+    assert e32 <= 4.0 * spread and e <= 1e-3
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_transfers_and_spmv_fp64(name, torch):
+    """The boundary's FP64 calls on 16-column vectors: restriction and
+    prolongation on every level pair, the level-0 product; products on a
+    coarser level are refused (no packed FP64 copy there)."""
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    rng = np.random.default_rng(24)
+    for l in range(H.nlev - 1):
+        R = H.R[l]
+        Lf, Lc = R.shape
+        rf = rng.uniform(-1, 1, (Lf, K))
+        rc = S.vec(l + 1)
+        B.xdg_restrict(S.h, l, S.vec(l, rf), rc)
+        er = _rel(_cols(rc.cpu().numpy(), Lc), R.T @ rf)
+        xc = rng.uniform(-1, 1, (Lc, K))
+        xf0 = rng.uniform(-1, 1, (Lf, K))
+        xf = S.vec(l, xf0)
+        B.xdg_prolong(S.h, l, S.vec(l + 1, xc), xf)
+        ep = _rel(_cols(xf.cpu().numpy(), Lf), xf0 + R @ xc)
+        _log(f"  {name} level {l}: 16-column restrict {er:.2e} prolong {ep:.2e}")
+        assert er <= 1e-13 and ep <= 1e-13
+    L = H.A[0].shape[0]
+    X = rng.uniform(-1, 1, (L, K))
+    Y = S.vec(0)
+    B.xdg_spmv(S.h, 0, S.vec(0, X), Y)
+    e = _rel(_cols(Y.cpu().numpy(), L), H.A[0] @ X)
+    _log(f"  {name}: 16-column xdg_spmv {e:.2e}")
+    assert e <= 1e-13
+    with pytest.raises(B.XdgError) as ei:
+        B.xdg_spmv(S.h, 1, S.vec(1), S.vec(1))
+    assert ei.value.code == B.XDG_EINVAL
+    # a buffer shorter than 16 columns is refused before the library is called
+    with pytest.raises(ValueError):
+        B.xdg_spmv(S.h, 0, S.vec(0)[: L * K - 1], Y)
+
+
+def _bsr_of(M, npc):
+    """Block rows (row_ptr, col_idx, row-major blocks) of a sparse matrix with
+    npc x npc blocks (an SPD matrix has every diagonal block)."""
+    import scipy.sparse as sp
+    Bm = sp.bsr_matrix(M.tocsr(), blocksize=(npc, npc))
+    Bm.sort_indices()
+    return Bm.indptr.astype(np.int32), Bm.indices.astype(np.int32), np.ascontiguousarray(Bm.data)
+
+
+@pytest.mark.parametrize("name", ["c2n8", "c4n8p4"])
+def test_coarse_solve_16(name, torch):
+    """The coarsest solve of the 16-column cycle on its own: a one-level
+    handle built from the oracle's coarsest Galerkin matrix, whose V-cycle is
+    z = fl32(C fl32(r)) with C the FP64 inverse.  Against the oracle's
+    Cholesky solve of the same FP32 input: the FP32 rounding of the result
+    plus the kappa bound of two FP64 inverses."""
+    from paper_2003_02431_amd import binding as B
+    pr, H, _ = _case(name, torch)
+    Ac = H.A[-1]
+    npc = H.np[-1]
+    rp, ci, val = _bsr_of(Ac, npc)
+    n_rows = len(rp) - 1
+    opt = B.options(krylov=B.XDG_FGMRES, precision=B.XDG_MIXED, nrhs=K, restart=20)
+    h = B.xdg_create(rp, ci, val, np.arange(n_rows + 1), [], opt,
+                     torch.cuda.current_stream().cuda_stream)
+    try:
+        n = Ac.shape[0]
+        r = np.random.default_rng(25).uniform(-1, 1, (n, K))
+        r32 = r.astype(np.float32).astype(np.float64)
+        rd = torch.as_tensor(r.reshape(-1)).cuda()
+        z = torch.zeros_like(rd)
+        B.xdg_vcycle(h, rd, z)
+        zg = z.cpu().numpy().reshape(n, K)
+        ref = np.linalg.solve(Ac.toarray(), r32)
+        kappa = np.linalg.cond(Ac.toarray())
+        e = _rel(zg, ref)
+        bound = U32 + max(1e-11, 50.0 * kappa * 2.0 ** -53)
+        _log(f"  {name}: 16-column coarse solve n={n} kappa={kappa:.1e} rel err {e:.2e} "
+             f"(bound {bound:.2e})")
+        assert e <= bound
+    finally:
+        B.xdg_destroy(h)
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -186,9 +186,17 @@ def test_pcg_solve(name, torch):
     assert rc == 0 and abs(it - ito) <= 1
     assert tr <= 1.05e-10 and abs(fr - tr) <= 1e-3 * tr
     assert hd <= 1e-6
-    # both iterates solve to 1e-10: their distance is bounded by the error
-    # bounds, kappa(A) * 1e-10 relative; in practice rounding alone separates them
     assert e <= 1e-8
+    # the FP64 contract: the iterate after exactly the oracle's iteration
+    # count matches the oracle's iterate to 1e-11 (only rounding order
+    # separates the two runs of the same recurrence)
+    B.xdg_set_tolerance(S.h, 1e-300, ito)
+    xk = S.vec(0)
+    rck, itk, _, _ = B.xdg_solve(S.h, S.vec(0, b), xk)
+    B.xdg_set_tolerance(S.h, 1e-10, 600)
+    ek = _rel(xk.cpu().numpy(), xo)
+    _log(f"  {name}: PCG iterate {itk} rel diff to the oracle's {ek:.2e}")
+    assert rck == B.XDG_ENOCONV and itk == ito and ek <= 1e-11
 
 
 @pytest.mark.parametrize("name", ["c1", "c2n16"])
@@ -418,6 +426,28 @@ def test_update_cells_equals_full_update(name, torch):
     rp = B.xdg_solve(Sp.h, b, xp)
     _log(f"  {name}: {cells.size} cells updated, solve it {rf[1]} / {rp[1]}")
     assert rf[0] == 0 and rp[0] == 0 and torch.equal(xf, xp)
+    # against the oracle's hierarchy of the changed values: every Galerkin
+    # level, sampled cell inverses and the solve
+    from oracle import mg
+    H2 = mg.Hierarchy(pr.row_ptr, pr.col_idx, val2, pr.cell_ptr, pr.transfers)
+    for l in range(nlev):
+        G = mg.block_matrix(*B.xdg_get_level_matrix(Sp.h, l))
+        d = abs(G - H2.A[l]).max() / abs(H2.A[l]).max()
+        assert d <= 1e-13, (l, d)
+    for l in range(nlev - 1):
+        _, invs = mg.cell_block_inverses(H2.A[l], H2.cell_ptr[l], H2.np[l])
+        lv_cells = cells if l == 0 else np.unique(np.linspace(0, len(invs) - 1, 20).astype(int))
+        for c in lv_cells[:40]:
+            Dg = B.xdg_get_cell_inverse(Sp.h, l, int(c))
+            assert _rel(Dg, invs[c]) <= _kappa_tol(np.linalg.cond(invs[c])), (l, c)
+    Ac = H2.A[-1].toarray()
+    kc = np.linalg.cond(Ac)
+    assert _rel(B.xdg_get_cell_inverse(Sp.h, nlev - 1, 0), np.linalg.inv(Ac)) <= _kappa_tol(kc)
+    xo, _, ito = mg.pcg(H2.A[0], pr.b, H2.vcycle, rtol=1e-10, maxit=600)
+    eo = _rel(xp.cpu().numpy(), xo)
+    _log(f"  {name}: partial update vs oracle hierarchy of the new values: solve it "
+         f"{rp[1]} (oracle {ito}), x rel diff {eo:.2e}")
+    assert abs(rp[1] - ito) <= 1 and eo <= 1e-8
     with pytest.raises(B.XdgError):
         B.xdg_update_cells(Sp.h, v2, [int(cells[0]), int(cells[0])])
     with pytest.raises(B.XdgError):
@@ -463,4 +493,38 @@ def test_full_size_sampled(torch):
     B.xdg_vcycle(S.h, S.vec(0, r2), z2)
     a, b = float(z1.cpu().numpy() @ r2), float(r1 @ z2.cpu().numpy())
     assert abs(a - b) <= 1e-10 * abs(a)
+    # two smoother sweeps on level 0 and one V-cycle against the oracle
+    # largest condition number of the cell blocks: every cut cell with two
+    # species (the ill-conditioned ones) and a sample of the others
+    cp0, A0 = H.cell_ptr[0], H.A[0].tocsr()
+    cand = np.union1d(np.flatnonzero(np.diff(cp0) == 2),
+                      np.linspace(0, len(cp0) - 2, 400).astype(int))
+    kmax = 1.0
+    for c in cand:
+        lo, hi = cp0[c] * pr.np, cp0[c + 1] * pr.np
+        kmax = max(kmax, np.linalg.cond(A0[lo:hi, lo:hi].toarray()))
+    bb, x0 = rng.uniform(-1, 1, (2, A.shape[0]))
+    xsw = S.vec(0, x0)
+    B.xdg_smooth(S.h, 0, S.vec(0, bb), xsw, 2)
+    esw = _rel(xsw.cpu().numpy(), mg.jacobi(H.A[0], H.Dinv[0], bb, x0, 0.7, 2))
+    kc = np.linalg.cond(H.A[-1].toarray())
+    ev = _rel(z1.cpu().numpy(), H.vcycle(r1))
+    _log(f"  32^3: two sweeps rel err {esw:.2e} (cell kappa {kmax:.1e}), V-cycle rel err "
+         f"{ev:.2e} (coarse kappa {kc:.1e})")
+    assert esw <= _kappa_tol(kmax) and ev <= _kappa_tol(kc)
+    # the FP64 contract at the benchmarked size: the PCG iterate after the
+    # oracle's iteration count (the plain-loop C++ oracle, pinned against the
+    # numpy one, runs the 32^3 solve on all host cores)
+    from oracle import mg_omp
+    if not os.path.exists(mg_omp.LIB):
+        mg_omp.build()
+    O = mg_omp.OmpHierarchy(pr)
+    xo, ho, ito = O.pcg(pr.b, rtol=1e-10, maxit=600)
+    O.close()
+    B.xdg_set_tolerance(S.h, 1e-300, ito)
+    xk = S.vec(0)
+    rck, itk, _, _ = B.xdg_solve(S.h, S.vec(0, pr.b), xk)
+    ek = _rel(xk.cpu().numpy(), xo)
+    _log(f"  32^3: PCG iterate {itk} (oracle converged in {ito}) rel diff {ek:.2e}")
+    assert rck == B.XDG_ENOCONV and itk == ito and abs(it - ito) <= 1 and ek <= 1e-11
     S.close()
