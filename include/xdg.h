@@ -150,6 +150,21 @@ int xdg_prolong(xdg_handle *h, int32_t level, const double *xc_dev, double *xf_d
  * (level-0 vectors; 16 columns on a 16-column handle). */
 int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
 
+/* xdg_vcycle for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same cycle with the same kernels and a bit-identical result, but the work
+ * vectors of every level live in one fixed device array of 2^22 doubles
+ * (32 MiB) that the library reserves once per device and keeps until the
+ * process ends.  The call makes no hipMalloc, hipFree or other allocating
+ * call.  Single-column handles with the block-Jacobi smoother only (else
+ * XDG_EINVAL).  The cycle needs about four doubles per level-0 unknown in
+ * FP64 and two in the FP32 cycle (the 32^3 p = 3 workload: about 2.7
+ * million in FP64); a larger one returns XDG_EINVAL.  Every call on one
+ * device shares the array and leaves its contents behind: calls that overlap
+ * on one device (other streams or threads) race, and the caller must order
+ * them.  r_dev read, z_dev overwritten (level-0 vectors). */
+int xdg_vcycle_noalloc(xdg_handle *h, const double *r_dev, double *z_dev);
+
 /* Solves M^0 x = b (Eq. GenericMatrixSystem on level 0) with the V-cycle
  * above as preconditioner of CG (XDG_CG; flexible CG with XDG_MIXED) or of
  * flexible GMRES(restart) with FP64 restarts (XDG_FGMRES), until the

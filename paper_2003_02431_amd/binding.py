@@ -64,6 +64,7 @@ def _load():
         "xdg_restrict": ([vp, C.c_int32, vp, vp], C.c_int),
         "xdg_prolong": ([vp, C.c_int32, vp, vp], C.c_int),
         "xdg_vcycle": ([vp, vp, vp], C.c_int),
+        "xdg_vcycle_noalloc": ([vp, vp, vp], C.c_int),
         "xdg_solve": ([vp, vp, vp, _f64p, C.c_int32, _i32p, _f64p], C.c_int),
         "xdg_level_info": ([vp, C.c_int32, _i32p, _i32p, _i32p], C.c_int),
         "xdg_get_level_matrix": ([vp, C.c_int32, _i32p, _i32p, _f64p], C.c_int),
@@ -97,7 +98,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("xdg_create", "xdg_spmv", "xdg_smooth", "xdg_restrict", "xdg_prolong",
-            "xdg_vcycle", "xdg_solve", "xdg_level_info", "xdg_get_level_matrix",
+            "xdg_vcycle", "xdg_vcycle_noalloc", "xdg_solve", "xdg_level_info", "xdg_get_level_matrix",
             "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_update_cells", "xdg_spmm", "xdg_setup_time",
             "xdg_mlp_param_count", "xdg_mlp_set", "xdg_mlp_get", "xdg_mlp_forward",
             "xdg_mlp_gradient", "xdg_mlp_train", "xdg_set_cell_features", "xdg_learned_pairs",
@@ -221,6 +222,10 @@ def xdg_prolong(h, level, xc, xf):
 
 def xdg_vcycle(h, r, z):
     return _check(_lib.xdg_vcycle(h, _vec(h, 0, r, "r"), _vec(h, 0, z, "z")))
+
+
+def xdg_vcycle_noalloc(h, r, z):
+    return _check(_lib.xdg_vcycle_noalloc(h, _vec(h, 0, r, "r"), _vec(h, 0, z, "z")))
 
 
 def xdg_solve(h, b, x, hist_cap=1000):

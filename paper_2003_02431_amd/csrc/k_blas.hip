@@ -105,6 +105,19 @@ __global__ void k_sqrt_scalar(double* scal, int i) {
 void launch_sqrt_scalar(hipStream_t s, double* scal, int i) {
     k_sqrt_scalar<<<1, 1, 0, s>>>(scal, i);
 }
+template <typename T>
+__global__ void k_fill_zero(int64_t n, T* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = T(0);
+}
+// x = 0 by a kernel (no memset node when the caller captures the stream)
+template <typename T>
+void launch_fill_zero(hipStream_t s, int64_t n, T* x) {
+    if (n > 0) k_fill_zero<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, x);
+}
+template void launch_fill_zero<double>(hipStream_t, int64_t, double*);
+template void launch_fill_zero<float>(hipStream_t, int64_t, float*);
+
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
     k_axpy<<<nblk(n, 256), 256, 0, s>>>(n, a, x, y);
 }

@@ -4,6 +4,8 @@
 // the Galerkin sparsity pattern, and sequences launches on the handle's stream.
 #include <numeric>
 
+#include <mutex>
+
 #include "xdg_handle.h"
 
 using namespace xdg;
@@ -211,7 +213,7 @@ static void smooth_from_zero(xdg_handle* h, Level& lv, int sweeps) {
     T*& y = P<T>::y(lv);
     const T om = (T)h->opt.omega;
     if (sweeps <= 0) {
-        (void)hipMemsetAsync(x, 0, lv.len() * sizeof(T), h->s);
+        launch_fill_zero<T>(h->s, lv.len(), x);
         return;
     }
     launch_jacobi<T>(h->s, true, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv), lv.doff,
@@ -306,6 +308,108 @@ static int apply_precond(xdg_handle* h, const double* r, double* z) {
 }
 
 // ---------------------------------------------------------------------------
+// V-cycle without allocation: the level work vectors live in a fixed device
+// array.  Device code names it; host code uses only its device address,
+// looked up once per device when a handle is created there.
+
+namespace {
+constexpr int64_t kScratchDoubles = int64_t(1) << 22;   // 32 MiB per device
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchDoubles];
+double* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(XDG_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return XDG_OK;
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(XDG_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch[dev] = static_cast<double*>(p);
+    return XDG_OK;
+}
+
+// the work vectors of one level that the V-cycle touches
+struct CyclePtrs {
+    double *b64 = nullptr, *x64 = nullptr, *y64 = nullptr, *r64 = nullptr;
+    float *b32 = nullptr, *x32 = nullptr, *y32 = nullptr, *r32 = nullptr;
+};
+constexpr int kMaxCycleLevels = 32;
+
+// Lays the V-cycle's work vectors out in 256-byte aligned pieces from base
+// (base = nullptr: only counts) and returns the doubles used.  Every level
+// holds b, x, y and, above a dense transfer, r in the cycle's precision; the
+// coarsest level holds b, x (and b64, x64 for the FP32 cycle's FP64 solve).
+int64_t carve_cycle(const xdg_handle* h, double* base, CyclePtrs* out) {
+    int64_t used = 0;
+    auto take = [&](int64_t n, int64_t word) -> char* {
+        char* p = base ? reinterpret_cast<char*>(base + used) : nullptr;
+        used += ((n * word + 255) / 256) * 32;
+        return p;
+    };
+    const int nl = (int)h->L.size();
+    for (int l = 0; l < nl; ++l) {
+        const Level& lv = h->L[l];
+        const int64_t n = lv.len();
+        const bool last = l == nl - 1;
+        CyclePtrs c;
+        if (h->mixed) {
+            c.b32 = reinterpret_cast<float*>(take(n, 4));
+            c.x32 = reinterpret_cast<float*>(take(n, 4));
+            if (!last) c.y32 = reinterpret_cast<float*>(take(n, 4));
+            if (!last && lv.t_kind == XDG_T_DENSE) c.r32 = reinterpret_cast<float*>(take(n, 4));
+            if (last) {
+                c.b64 = reinterpret_cast<double*>(take(n, 8));
+                c.x64 = reinterpret_cast<double*>(take(n, 8));
+            }
+        } else {
+            c.b64 = reinterpret_cast<double*>(take(n, 8));
+            c.x64 = reinterpret_cast<double*>(take(n, 8));
+            if (!last) c.y64 = reinterpret_cast<double*>(take(n, 8));
+            if (!last && lv.t_kind == XDG_T_DENSE) c.r64 = reinterpret_cast<double*>(take(n, 8));
+        }
+        if (out) out[l] = c;
+    }
+    return used;
+}
+
+void swap_cycle_ptrs(Level& lv, CyclePtrs& c) {
+    std::swap(lv.b64, c.b64);
+    std::swap(lv.x64, c.x64);
+    std::swap(lv.y64, c.y64);
+    std::swap(lv.r64, c.r64);
+    std::swap(lv.b32, c.b32);
+    std::swap(lv.x32, c.x32);
+    std::swap(lv.y32, c.y32);
+    std::swap(lv.r32, c.r32);
+}
+}  // namespace
+
+extern "C" int xdg_vcycle_noalloc(xdg_handle* h, const double* r, double* z) {
+    if (!h || !r || !z) return fail(XDG_EINVAL, "xdg_vcycle_noalloc: NULL argument");
+    if (h->nrhs != 1 || h->opt.smoother != XDG_JACOBI)
+        return fail(XDG_EINVAL, "xdg_vcycle_noalloc: single-column handles with the block-Jacobi "
+                                "smoother only");
+    if ((int)h->L.size() > kMaxCycleLevels)
+        return fail(XDG_EINVAL, "xdg_vcycle_noalloc: more than 32 levels");
+    if (h->dev < 0 || h->dev >= kMaxDevices || !g_scratch[h->dev])
+        return fail(XDG_EINVAL, "xdg_vcycle_noalloc: no scratch address for the handle's device");
+    const int64_t need = carve_cycle(h, nullptr, nullptr);
+    if (need > kScratchDoubles)
+        return fail(XDG_EINVAL, "xdg_vcycle_noalloc: the cycle needs " + std::to_string(need) +
+                                    " doubles of work space, the fixed array holds " +
+                                    std::to_string(kScratchDoubles));
+    CyclePtrs ptrs[kMaxCycleLevels];
+    carve_cycle(h, g_scratch[h->dev], ptrs);
+    const int nl = (int)h->L.size();
+    for (int l = 0; l < nl; ++l) swap_cycle_ptrs(h->L[l], ptrs[l]);     // scratch in
+    const int rc = apply_precond(h, r, z);
+    for (int l = 0; l < nl; ++l) swap_cycle_ptrs(h->L[l], ptrs[l]);     // handle's back
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // public API
 
 extern "C" const char* xdg_last_error(void) { return xdg::last_error_text().c_str(); }
@@ -381,6 +485,9 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     if ((int64_t)nr * npf > 16384)
         return fail(XDG_EINVAL, "xdg_create: coarsest level too large for the dense solve");
 
+    // device work starts here (validation above touches no device)
+    HIPCHK(hipGetDevice(&h->dev));
+    CHK(scratch_setup(h->dev));
     h->opt = *opt;
     h->mixed = opt->precision == XDG_MIXED;
     h->nrhs = opt->nrhs;

@@ -94,6 +94,7 @@ using xdg::P;
 
 struct xdg_handle {
     hipStream_t s = nullptr;
+    int dev = 0;                    // device current at xdg_create
     xdg_options opt{};
     std::vector<Level> L;
     int cn = 0, cld = 0;            // coarsest order, padded leading dimension

@@ -83,6 +83,8 @@ void launch_cg_update_p(hipStream_t s, int64_t n, const double* scal, int i_new,
 void launch_fcg_update_p(hipStream_t s, int64_t n, const double* scal, int i_zq, int i_pq,
                          const double* z, double* p);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);
+template <typename T>
+void launch_fill_zero(hipStream_t s, int64_t n, T* x);
 void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y);
 
 }  // namespace xdg
