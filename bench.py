@@ -128,20 +128,20 @@ class _Cached:
         return pr
 
 
-def load_problem(n, seed, workload="c2", p=3):
+def load_problem(n, seed, workload="c2", p=3, hier="p1h"):
     """Generate the workload (or reuse a copy saved by an earlier run of this
     benchmark in the same session when XDG_BENCH_CACHE names a directory).
     c5: the 64^3 ellipsoid family with one right-hand side plus the learned
     smoother's cell features."""
     from xdg_inputs import problems
     cache = os.environ.get("XDG_BENCH_CACHE")
-    tag = {"c2": f"c2_n{n}_s{seed}", "c4": f"c4_n{n}_p{p}_s{seed}",
+    tag = {"c2": f"c2_n{n}_s{seed}_{hier}", "c4": f"c4_n{n}_p{p}_s{seed}",
            "c5": f"c5_n{n}_p{p}_s{seed}"}[workload]
     path = os.path.join(cache, tag + ".npz") if cache else None
     if path and os.path.exists(path):
         return _Cached.load(path)
     if workload == "c2":
-        pr = problems.c2(seed=seed, n=n)
+        pr = problems.c2(seed=seed, n=n, hier=problems.hierarchy(hier, n, 3))
     elif workload == "c4":
         pr = problems.c4(seed=seed, n=n, p=p, nrhs=16, verbose=True)
     else:
@@ -339,6 +339,67 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_moving(args):
+    """A moving-interface step at 32^3 p=3 (sphere r 0.6 shifted by
+    (0.3, 0.2, -0.1) h, f = 1, mu 1 | 1000): after the t0 solve the t1 space
+    has a new agglomeration (new block pattern), so the step is a new handle
+    (upload, symbolic and numeric set-up), the L2 re-projection of the t0
+    solution onto the t1 space, and the t1 solve from it (FP64 CG to 1e-8)."""
+    import torch
+    from paper_2003_02431_amd import binding as B
+    from xdg_inputs import problems
+    from xdg_inputs.moving import moving_pair
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    pr0, pr1, Pi = moving_pair(n=args.n, p=3, c0=(0.01, -0.02, 0.015), shift=(0.3, 0.2, -0.1),
+                               hierarchy=problems.hierarchy(args.hier, args.n, 3), verbose=True)
+    log(f"[bench-moving] two time levels generated in {time.time() - t0:.1f}s: rows "
+        f"{pr0.n_rows} -> {pr1.n_rows}")
+    opt = B.options(krylov=B.XDG_CG, rtol=1e-8, maxit=1000)
+    S0 = B.Solver(pr0, opt)
+    x0 = S0.vec(0)
+    B.xdg_solve(S0.h, S0.vec(0, pr0.b), x0)
+    b1 = torch.as_tensor(np.ascontiguousarray(pr1.b)).cuda()
+    rows = []
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S1 = B.Solver(pr1, opt)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        B.xdg_set_projection(S1.h, Pi["row_ptr"], Pi["col_idx"], Pi["val"], Pi["n_cols"])
+        g = S1.vec(0)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        B.xdg_project(S1.h, x0, g)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        rc, it, fr, _ = B.xdg_solve(S1.h, b1, g, hist_cap=2000)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        xz = S1.vec(0)
+        rcz, itz, _, _ = B.xdg_solve(S1.h, b1, xz, hist_cap=2000)
+        S1.close()
+        if k >= args.warmup:
+            rows.append((t2 - t1, t3 - t2, t4 - t3, t5 - t4, it, itz))
+        log(f"[bench-moving] step {k}: create {1e3 * (t2 - t1):.1f} ms, operator upload "
+            f"{1e3 * (t3 - t2):.1f} ms, projection {1e3 * (t4 - t3):.3f} ms, solve "
+            f"{1e3 * (t5 - t4):.1f} ms ({it} iterations; {itz} from zero)")
+    S0.close()
+    med = np.median(np.array([r[:4] for r in rows]), axis=0)
+    out = {"metric": "moving-interface step time (s): re-agglomerated handle + L2 re-projection "
+                     "+ FP64 CG solve to rel.res 1e-8, 3D p=3 cut grid",
+           "value": round(float(med.sum()), 5), "unit": "s", "higher_is_better": False,
+           "config": {"workload": f"xdg_sip_poisson_3d_p3_{args.n}^3_moving_sphere_r0.6",
+                      "rows_t0": int(pr0.n_rows), "rows_t1": int(pr1.n_rows),
+                      "nnzb_t1": int(pr1.col_idx.size), "hierarchy": args.hier},
+           "create_s": round(float(med[0]), 5), "operator_upload_s": round(float(med[1]), 5),
+           "projection_s": round(float(med[2]), 6), "solve_s": round(float(med[3]), 5),
+           "iters_from_projection": rows[-1][4], "iters_from_zero": rows[-1][5],
+           "note": "create = host-to-device copy of the t1 system and its hierarchy set-up"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,14 +409,19 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "moving"],
                     help="c2: 32^3 p=3 single right-hand side (default line); "
                          "c4: 64^3 cut grid with 16 right-hand sides; "
                          "c5: 64^3 p=3 with the learned smoother")
     ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--hier", default="p1h", choices=["p1h", "h3p1", "hp", "h2p"],
+                    help="coarse-level sequence of the 32^3 workload (xdg_inputs.problems."
+                         "hierarchy)")
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--profile-spmv", action="store_true",
                     help="only launch the level-0 SpMV 20 times and a plain copy (counters)")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="only run three FP64 set-up + solve steps (kernel statistics)")
     ap.add_argument("--profile-mixed", action="store_true",
                     help="only run two mixed-precision flexible-CG solves and a plain copy "
                          "(counters of the FP32 kernels)")
@@ -365,6 +431,9 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "moving":
+        bench_moving(args)
+        return
     if args.workload in ("c4", "c5"):
         if args.n == 32:
             args.n = 64
@@ -378,7 +447,7 @@ def main():
     torch.cuda.set_device(0)
     log(f"[bench] generating c2 workload n={args.n} seed={args.seed}")
     t0 = time.time()
-    pr = load_problem(args.n, args.seed)
+    pr = load_problem(args.n, args.seed, hier=args.hier)
     log(f"[bench] generated rows={pr.n_rows} nnzb={pr.col_idx.size} in {time.time() - t0:.1f}s")
 
     opt8 = B.options(krylov=B.XDG_CG, rtol=1e-8, maxit=1000)
@@ -395,6 +464,17 @@ def main():
         out.copy_(big)
         torch.cuda.synchronize()
         log(f"[bench] profile-spmv: 20 launches, bytes/launch {spmv_bytes(pr)}; copy 1 GiB")
+        return
+
+    if args.profile_solve:
+        val_dev = torch.as_tensor(np.ascontiguousarray(pr.val)).cuda()
+        b_dev = S.vec(0, pr.b)
+        for _ in range(3):
+            x_dev = S.vec(0)
+            B.xdg_update_matrix(S.h, val_dev)
+            rc, it, fr, _ = B.xdg_solve(S.h, b_dev, x_dev, hist_cap=2000)
+        torch.cuda.synchronize()
+        log(f"[bench] profile-solve: 3 set-up + FP64 CG solves ({it} iterations each)")
         return
 
     if args.profile_mixed:

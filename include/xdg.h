@@ -233,6 +233,30 @@ int xdg_update_matrix(xdg_handle *h, const double *val_dev);
 int xdg_update_cells(xdg_handle *h, const double *val_dev, int32_t n,
                      const int32_t *cells_host);
 
+/* Block-sparse operator from the level-0 space of an earlier time level
+ * (n_cols block rows of np modes) into the level-0 space of this handle: the
+ * L2 re-projection that Section 2.3 prescribes between time steps (the
+ * finished step's solution, injected into the non-agglomerated cut-cell
+ * space, projected onto the agglomerated space of the next step, whose
+ * agglomeration map -- and so the block pattern of this handle -- may
+ * differ).  Block b of row i is P[m(i, r), m_old(col_idx[b], c)] =
+ * val[b*np*np + r*np + c]; n_rows and np must equal level 0's.  Host arrays,
+ * copied (they may be freed on return); replaces an earlier operator. */
+typedef struct {
+    int32_t n_rows, n_cols, np, nnzb;
+    const int32_t *row_ptr;   /* [n_rows + 1], row_ptr[0] = 0, row_ptr[n_rows] = nnzb */
+    const int32_t *col_idx;   /* [nnzb], strictly increasing per row, in [0, n_cols) */
+    const double  *val;       /* [nnzb * np * np], finite */
+} xdg_projection;
+
+int xdg_set_projection(xdg_handle *h, const xdg_projection *P);
+
+/* x_new_dev = P x_old_dev with the operator of xdg_set_projection: x_old_dev
+ * holds n_cols * np doubles (the earlier level-0 vector), x_new_dev receives
+ * this handle's n_rows * np (a starting guess for xdg_solve).  Single-column
+ * handles; XDG_EINVAL without an operator. */
+int xdg_project(xdg_handle *h, const double *x_old_dev, double *x_new_dev);
+
 /* New stopping rule for later xdg_solve calls: rtol > 0, maxit >= 1. */
 int xdg_set_tolerance(xdg_handle *h, double rtol, int32_t maxit);
 

@@ -21,6 +21,17 @@ def block_matrix(row_ptr, col_idx, val):
                          shape=(n_rows * Np, n_rows * Np)).tocsr()
 
 
+def block_operator(row_ptr, col_idx, val, n_cols):
+    """A rectangular block operator (n_rows block rows, n_cols block columns,
+    Np x Np blocks) as a sparse matrix: the L2 re-projection between the
+    agglomerated spaces of two time levels (Section 2.3) is applied as
+    x_new = P x_old."""
+    n_rows = len(row_ptr) - 1
+    Np = val.shape[1]
+    return sp.bsr_matrix((val, np.asarray(col_idx), np.asarray(row_ptr)),
+                         shape=(n_rows * Np, n_cols * Np)).tocsr()
+
+
 def transfer_matrix(T, n_rows_f, np_f):
     """R^{X,lambda} in R^{L_f x L_c} (Eq. XDGrestrictionMatrix): the
     coefficients of the coarse basis in the fine basis.  p-levels keep the

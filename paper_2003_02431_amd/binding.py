@@ -44,6 +44,11 @@ class xdg_transfer(C.Structure):
                 ("cell_ptr_c", _i32p)]
 
 
+class xdg_projection(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("np", C.c_int32),
+                ("nnzb", C.c_int32), ("row_ptr", _i32p), ("col_idx", _i32p), ("val", _f64p)]
+
+
 class xdg_options(C.Structure):
     _fields_ = [("krylov", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("precision", C.c_int32),
@@ -84,6 +89,8 @@ def _load():
         "xdg_learned_pairs": ([vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, vp, vp, _i32p],
                               C.c_int),
         "xdg_set_tolerance": ([vp, C.c_double, C.c_int32], C.c_int),
+        "xdg_set_projection": ([vp, C.POINTER(xdg_projection)], C.c_int),
+        "xdg_project": ([vp, vp, vp], C.c_int),
         "xdg_set_smoother": ([vp, C.c_int32, C.c_float], C.c_int),
         "xdg_learned_stats": ([vp, _i64p, _i32p], C.c_int),
         "xdg_destroy": ([vp], None),
@@ -102,7 +109,8 @@ EXPORTED = ("xdg_create", "xdg_spmv", "xdg_smooth", "xdg_restrict", "xdg_prolong
             "xdg_get_cell_inverse", "xdg_update_matrix", "xdg_update_cells", "xdg_spmm", "xdg_setup_time",
             "xdg_mlp_param_count", "xdg_mlp_set", "xdg_mlp_get", "xdg_mlp_forward",
             "xdg_mlp_gradient", "xdg_mlp_train", "xdg_set_cell_features", "xdg_learned_pairs",
-            "xdg_set_smoother", "xdg_learned_stats", "xdg_set_tolerance", "xdg_destroy",
+            "xdg_set_smoother", "xdg_learned_stats", "xdg_set_tolerance",
+            "xdg_set_projection", "xdg_project", "xdg_destroy",
             "xdg_last_error")
 
 
@@ -361,6 +369,27 @@ def xdg_learned_pairs(h, b, xk, xs, cell0, cell_step, X, T, clip=0.0):
     return n.value
 
 
+_PROJ = {}     # handle address -> length of the earlier level-0 vector
+
+
+def xdg_set_projection(h, row_ptr, col_idx, val, n_cols):
+    """The L2 re-projection operator from an earlier space of n_cols block
+    rows into this handle's level 0 (host arrays, row-major blocks)."""
+    rp, ci = _np(row_ptr, np.int32), _np(col_idx, np.int32)
+    v = _np(val, np.float64)
+    P = xdg_projection(len(rp) - 1, int(n_cols), v.shape[1], len(ci), rp.ctypes.data_as(_i32p),
+                       ci.ctypes.data_as(_i32p), v.ctypes.data_as(_f64p))
+    rc = _check(_lib.xdg_set_projection(h, C.byref(P)))
+    _PROJ[_key(h)] = int(n_cols) * v.shape[1]
+    return rc
+
+
+def xdg_project(h, x_old, x_new):
+    p_old = _ptr(x_old)
+    _need(x_old, _PROJ.get(_key(h), 0), "x_old")
+    return _check(_lib.xdg_project(h, p_old, _vec(h, 0, x_new, "x_new")))
+
+
 def xdg_set_tolerance(h, rtol, maxit):
     return _check(_lib.xdg_set_tolerance(h, rtol, maxit))
 
@@ -377,6 +406,7 @@ def xdg_learned_stats(h):
 
 def xdg_destroy(h):
     _HANDLES.pop(_key(h), None)
+    _PROJ.pop(_key(h), None)
     _lib.xdg_destroy(h)
 
 

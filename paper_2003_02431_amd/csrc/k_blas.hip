@@ -50,6 +50,30 @@ __global__ void k_cg_update_xr(int64_t n, const double* __restrict__ scal, int i
     r[i] -= alpha * q[i];
 }
 
+// the CG update and the partial sums of the new r . r over the grid of
+// k_dot_partial (same threads, same order)
+__global__ __launch_bounds__(256) void k_cg_update_xr_dot(int64_t n,
+                                                          const double* __restrict__ scal,
+                                                          int i_rz, int i_pq,
+                                                          const double* __restrict__ p,
+                                                          const double* __restrict__ q,
+                                                          double* __restrict__ x,
+                                                          double* __restrict__ r,
+                                                          double* __restrict__ partial) {
+    __shared__ double sh[4];
+    const double alpha = scal[i_rz] / scal[i_pq];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
 // p = z + beta p with beta = scal[i_new] / scal[i_old]
 __global__ void k_cg_update_p(int64_t n, const double* __restrict__ scal, int i_new, int i_old,
                               const double* __restrict__ z, double* __restrict__ p) {
@@ -87,6 +111,32 @@ void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, doub
 void launch_cg_update_xr(hipStream_t s, int64_t n, const double* scal, int i_rz, int i_pq,
                          const double* p, const double* q, double* x, double* r) {
     k_cg_update_xr<<<nblk(n, 256), 256, 0, s>>>(n, scal, i_rz, i_pq, p, q, x, r);
+}
+void launch_cg_update_xr_dot(hipStream_t s, int64_t n, double* scal, int i_rz, int i_pq,
+                             int i_rr, const double* p, const double* q, double* x, double* r,
+                             double* partial) {
+    k_cg_update_xr_dot<<<kDotBlocks, 256, 0, s>>>(n, scal, i_rz, i_pq, p, q, x, r, partial);
+    k_dot_final<<<1, 256, 0, s>>>(partial, kDotBlocks, scal + i_rr);
+}
+// fixed-order sum of many partials (one per workgroup of a fused product):
+// 1024 threads, coalesced strided reads, then the wave and workgroup trees
+__global__ __launch_bounds__(1024) void k_dot_final_wide(const double* __restrict__ partial,
+                                                         int np, double* __restrict__ out) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+        *out = t;
+    }
+}
+void launch_dot_final(hipStream_t s, const double* partial, int np, double* out) {
+    k_dot_final_wide<<<1, 1024, 0, s>>>(partial, np, out);
 }
 void launch_cg_update_p(hipStream_t s, int64_t n, const double* scal, int i_new, int i_old,
                         const double* z, double* p) {

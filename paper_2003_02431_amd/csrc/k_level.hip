@@ -155,21 +155,26 @@ __device__ __forceinline__ T row_times_x_rt(int beg, int end, const int* __restr
 // first half of the row's blocks and the rest), their sums combined through
 // LDS in a fixed order -- twice the waves, which shortens the tail of the
 // grid (measured 131.4 -> 127.9 us at 32^3 p=3).
+// MODE SPMV_AX_DOT (Np >= 16): y = A x and, per workgroup, the partial inner
+// product x . y of its two rows (fixed order: lanes, then row 0 + row 1) in
+// dpart[blockIdx.x].
 template <typename T, int NP, int MODE>
 __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const int* __restrict__ rp,
                                                   const int* __restrict__ ci,
                                                   const T* __restrict__ A,
                                                   const T* __restrict__ x,
                                                   const T* __restrict__ b, T* __restrict__ y,
-                                                  int npc) {
+                                                  int npc, double* __restrict__ dpart, int rev) {
     const int lane = threadIdx.x & 63;
     if constexpr (NP >= 16) {
         using R = RowCfg<T, NP, true>;
         __shared__ T part[2][NP];
+        __shared__ double rowdot[2];
         const int w = threadIdx.x >> 6;
-        const int row = uniform(blockIdx.x * 2 + (w >> 1));
+        const int row0 = uniform(blockIdx.x * 2 + (w >> 1));
         const int half = w & 1;
-        const bool valid = row < n_rows;
+        const bool valid = row0 < n_rows;
+        const int row = rev ? n_rows - 1 - row0 : row0;
         int beg = 0, nb = 0;
         if (valid) {
             const int b0 = uniform(rp[row]), n = uniform(rp[row + 1]) - b0;
@@ -187,20 +192,29 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const i
             for (int v = 0; v < R::VEC; ++v) part[w >> 1][lane * R::VEC + v] = acc[v];
         }
         __syncthreads();
+        double dot = 0.0;
         if (!half && valid && lane < R::L) {
 #pragma unroll
             for (int v = 0; v < R::VEC; ++v) {
                 const int r = lane * R::VEC + v;
                 const T sum = acc[v] + part[w >> 1][r];
                 const int64_t o = (int64_t)row * NP + r;
-                if (MODE == SPMV_AX) y[o] = sum;
+                if (MODE == SPMV_AX || MODE == SPMV_AX_DOT) y[o] = sum;
                 else if (MODE == SPMV_RESID) y[o] = b[o] - sum;
                 else if (r < npc) y[(int64_t)row * npc + r] = b[o] - sum;
+                if (MODE == SPMV_AX_DOT) dot += (double)x[o] * (double)sum;
             }
         }
+        if constexpr (MODE == SPMV_AX_DOT) {
+            for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+            if (!half && lane == 0) rowdot[w >> 1] = dot;
+            __syncthreads();
+            if (threadIdx.x == 0) dpart[blockIdx.x] = rowdot[0] + rowdot[1];
+        }
     } else {
-        const int row = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-        if (row >= n_rows) return;
+        const int row0 = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+        if (row0 >= n_rows) return;
+        const int row = rev ? n_rows - 1 - row0 : row0;
         const int beg = uniform(rp[row]), end = uniform(rp[row + 1]);
         if constexpr (NP > 0) {
             using R = RowCfg<T, NP>;
@@ -272,13 +286,14 @@ __global__ __launch_bounds__(256) void k_jacobi(int n_cells, int np_rt, const in
                                                 const T* __restrict__ D,
                                                 const T* __restrict__ b,
                                                 const T* __restrict__ xin,
-                                                T* __restrict__ xout, T omega) {
+                                                T* __restrict__ xout, T omega, int rev) {
     __shared__ T res[4][kMaxCell];
     const int np = NP ? NP : np_rt;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int cell = uniform(blockIdx.x * 4 + w);
-    if (cell >= n_cells) return;
+    const int cell0 = uniform(blockIdx.x * 4 + w);
+    if (cell0 >= n_cells) return;
+    const int cell = rev ? n_cells - 1 - cell0 : cell0;
     const int r0 = uniform(cell_ptr[cell]), r1 = uniform(cell_ptr[cell + 1]);
     const int nc = (r1 - r0) * np;
     for (int row = r0; row < r1; ++row) {
@@ -541,6 +556,78 @@ __global__ __launch_bounds__(256) void k_restrict_dense(int n_c, int npf, int np
     }
 }
 
+// Coarse blocks of more than kMaxTransferModes modes (aggregation levels that
+// keep the fine degree, R_i up to 35 x 35): the restriction runs in two
+// kernels so that no wave walks all children of a coarse row in sequence.
+// (1) one wave per fine row i: t_i = R_i^T rf_i; lane = (coarse mode m,
+//     group g), the G = 64 / npc groups take the fine modes a = g, g + G, ...
+//     (npc consecutive lanes read one contiguous row of R_i), then a fixed
+//     tree over the groups;
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_rows_wide(int n_f, int npf, int npc,
+                                                            const T* __restrict__ R,
+                                                            const T* __restrict__ rf,
+                                                            T* __restrict__ t) {
+    const int lane = threadIdx.x & 63;
+    const int i = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (i >= n_f) return;
+    const int G = 64 / npc;
+    const int m = lane % npc, g = lane / npc;
+    const T* Ri = R + (int64_t)i * npf * npc;
+    const T* ri = rf + (int64_t)i * npf;
+    T acc = 0;
+    if (g < G)
+        for (int a = g; a < npf; a += G) acc += Ri[a * npc + m] * ri[a];
+    for (int st = 1; st < G; st <<= 1) {
+        const T o = __shfl(acc, min(lane + st * npc, 63), 64);
+        if (g % (2 * st) == 0 && g + st < G) acc += o;
+    }
+    if (lane < npc) t[(int64_t)i * npc + lane] = acc;
+}
+
+// (2) rc[c][m] = sum over the children of c, in ascending order, of t_i[m].
+template <typename T>
+__global__ void k_restrict_children(int n_c, int npc, const int* __restrict__ child_ptr,
+                                    const int* __restrict__ child_idx, const T* __restrict__ t,
+                                    T* __restrict__ rc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n_c * npc) return;
+    const int c = (int)(e / npc), m = (int)(e - (int64_t)c * npc);
+    T acc = 0;
+    for (int q = child_ptr[c]; q < child_ptr[c + 1]; ++q)
+        acc += t[(int64_t)child_idx[q] * npc + m];
+    rc[e] = acc;
+}
+
+// Prolongation for the same wide transfers, one wave per fine row i:
+// xf_i += R_i xc_{parent(i)}; lane = (coarse mode m, group g) reads one
+// contiguous row segment of R_i per fine mode a = g, g + G, ...; the products
+// of a row are summed over the npc lanes of the group by a fixed tree.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_rows_wide(int n_f, int npf, int npc,
+                                                           const int* __restrict__ parent,
+                                                           const T* __restrict__ R,
+                                                           const T* __restrict__ xc,
+                                                           T* __restrict__ xf) {
+    const int lane = threadIdx.x & 63;
+    const int i = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (i >= n_f) return;
+    const int G = 64 / npc;
+    const int m = lane % npc, g = lane / npc;
+    const T* Ri = R + (int64_t)i * npf * npc;
+    const T xm = g < G ? xc[(int64_t)parent[i] * npc + m] : T(0);
+    const int steps = (npf + G - 1) / G;
+    for (int k = 0; k < steps; ++k) {
+        const int a = g + k * G;
+        T v = (g < G && a < npf) ? Ri[a * npc + m] * xm : T(0);
+        for (int st = 1; st < npc; st <<= 1) {
+            const T o = __shfl(v, min(lane + st, 63), 64);
+            if (m % (2 * st) == 0 && m + st < npc) v += o;
+        }
+        if (g < G && a < npf && m == 0) xf[(int64_t)i * npf + a] += v;
+    }
+}
+
 // xf[i][a] += sum_m R_i[a][m] xc[parent(i)][m]
 template <typename T>
 __global__ void k_prolong_dense(int n_f, int npf, int npc, const int* __restrict__ parent,
@@ -586,7 +673,7 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 
 template <typename T, int MODE>
 static void spmv_np(hipStream_t s, int n_rows, int np, const int* rp, const int* ci, const T* A,
-                    const T* x, const T* b, T* y, int npc) {
+                    const T* x, const T* b, T* y, int npc, int rev) {
     dim3 g(nblk(n_rows, 4)), blk(256);
     dim3 gg(nblk(n_rows, 256 / kGS));
     switch (np) {
@@ -595,32 +682,53 @@ static void spmv_np(hipStream_t s, int n_rows, int np, const int* rp, const int*
         XDG_NPG(1) XDG_NPG(3) XDG_NPG(4) XDG_NPG(6)
 #undef XDG_NPG
 #define XDG_NP(N) \
-    case N: k_bsr_spmv<T, N, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc); break;
+    case N: k_bsr_spmv<T, N, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc, nullptr, rev); break;
         XDG_NP(10)
 #undef XDG_NP
 #define XDG_NP2(N)                                                                          \
     case N:                                                                                 \
         k_bsr_spmv<T, N, MODE><<<nblk(n_rows, 2), blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, \
-                                                                npc);                       \
+                                                                npc, nullptr, rev);         \
         break;
         XDG_NP2(20) XDG_NP2(35)
 #undef XDG_NP2
-        default: k_bsr_spmv<T, 0, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc);
+        default: k_bsr_spmv<T, 0, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc, nullptr, rev);
     }
 }
 
 template <typename T>
 void launch_spmv(hipStream_t s, int mode, int n_rows, int np, const int* rp, const int* ci,
-                 const T* A, const T* x, const T* b, T* y, int npc) {
-    if (mode == SPMV_AX) spmv_np<T, SPMV_AX>(s, n_rows, np, rp, ci, A, x, b, y, npc);
-    else if (mode == SPMV_RESID) spmv_np<T, SPMV_RESID>(s, n_rows, np, rp, ci, A, x, b, y, npc);
-    else spmv_np<T, SPMV_RESID_TRUNC>(s, n_rows, np, rp, ci, A, x, b, y, npc);
+                 const T* A, const T* x, const T* b, T* y, int npc, bool rev) {
+    const int r = rev ? 1 : 0;
+    if (mode == SPMV_AX) spmv_np<T, SPMV_AX>(s, n_rows, np, rp, ci, A, x, b, y, npc, r);
+    else if (mode == SPMV_RESID) spmv_np<T, SPMV_RESID>(s, n_rows, np, rp, ci, A, x, b, y, npc, r);
+    else spmv_np<T, SPMV_RESID_TRUNC>(s, n_rows, np, rp, ci, A, x, b, y, npc, r);
+}
+
+// y = A x and *out = x . y (FP64, Np = 20 or 35: the product's epilogue forms
+// per-workgroup partials, a second kernel adds them in order); false when the
+// block size has no fused form (the caller then runs the two steps apart)
+bool launch_spmv_dot(hipStream_t s, int n_rows, int np, const int* rp, const int* ci,
+                     const double* A, const double* x, double* y, double* partial,
+                     double* out, bool rev) {
+    const unsigned nb = nblk(n_rows, 2);
+    const int r = rev ? 1 : 0;
+    if (np == 20)
+        k_bsr_spmv<double, 20, SPMV_AX_DOT><<<nb, 256, 0, s>>>(n_rows, np, rp, ci, A, x, nullptr,
+                                                               y, 0, partial, r);
+    else if (np == 35)
+        k_bsr_spmv<double, 35, SPMV_AX_DOT><<<nb, 256, 0, s>>>(n_rows, np, rp, ci, A, x, nullptr,
+                                                               y, 0, partial, r);
+    else
+        return false;
+    launch_dot_final(s, partial, (int)nb, out);
+    return true;
 }
 
 template <typename T, bool FIRST>
 static void jacobi_np(hipStream_t s, int n_cells, int np, const int* cp, const int* rp,
                       const int* ci, const T* A, const int64_t* doff, const T* D, const T* b,
-                      const T* xin, T* xout, T omega) {
+                      const T* xin, T* xout, T omega, int rev) {
     dim3 g(nblk(n_cells, 4)), blk(256);
     dim3 gg(nblk(n_cells, 256 / kGS));
     switch (np) {
@@ -634,22 +742,23 @@ static void jacobi_np(hipStream_t s, int n_cells, int np, const int* cp, const i
 #define XDG_NP(N)                                                                       \
     case N:                                                                             \
         k_jacobi<T, N, FIRST><<<g, blk, 0, s>>>(n_cells, np, cp, rp, ci, A, doff, D, b, \
-                                                 xin, xout, omega);                     \
+                                                 xin, xout, omega, rev);                \
         break;
         XDG_NP(10) XDG_NP(20) XDG_NP(35)
 #undef XDG_NP
         default:
             k_jacobi<T, 0, FIRST><<<g, blk, 0, s>>>(n_cells, np, cp, rp, ci, A, doff, D, b, xin,
-                                                     xout, omega);
+                                                     xout, omega, rev);
     }
 }
 
 template <typename T>
 void launch_jacobi(hipStream_t s, bool first, int n_cells, int np, const int* cp, const int* rp,
                    const int* ci, const T* A, const int64_t* doff, const T* D, const T* b,
-                   const T* xin, T* xout, T omega) {
-    if (first) jacobi_np<T, true>(s, n_cells, np, cp, rp, ci, A, doff, D, b, xin, xout, omega);
-    else jacobi_np<T, false>(s, n_cells, np, cp, rp, ci, A, doff, D, b, xin, xout, omega);
+                   const T* xin, T* xout, T omega, bool rev) {
+    const int r = rev ? 1 : 0;
+    if (first) jacobi_np<T, true>(s, n_cells, np, cp, rp, ci, A, doff, D, b, xin, xout, omega, r);
+    else jacobi_np<T, false>(s, n_cells, np, cp, rp, ci, A, doff, D, b, xin, xout, omega, r);
 }
 
 template <typename T>
@@ -661,15 +770,24 @@ void launch_prolong_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* 
     k_prolong_trunc<T><<<nblk((int64_t)n_rows * npc, 256), 256, 0, s>>>(n_rows, npf, npc, xc, xf);
 }
 template <typename T>
-void launch_restrict_dense(hipStream_t s, int n_c, int npf, int npc, const int* cptr,
-                           const int* cidx, const T* R, const T* rf, T* rc) {
-    k_restrict_dense<T><<<nblk(n_c, 4), 256, 0, s>>>(n_c, npf, npc, cptr, cidx, R, rf, rc);
+void launch_restrict_dense(hipStream_t s, int n_c, int n_f, int npf, int npc, const int* cptr,
+                           const int* cidx, const T* R, const T* rf, T* rc, T* tmp) {
+    if (npc <= kMaxTransferModes) {
+        k_restrict_dense<T><<<nblk(n_c, 4), 256, 0, s>>>(n_c, npf, npc, cptr, cidx, R, rf, rc);
+        return;
+    }
+    k_restrict_rows_wide<T><<<nblk(n_f, 4), 256, 0, s>>>(n_f, npf, npc, R, rf, tmp);
+    k_restrict_children<T><<<nblk((int64_t)n_c * npc, 256), 256, 0, s>>>(n_c, npc, cptr, cidx,
+                                                                          tmp, rc);
 }
 template <typename T>
 void launch_prolong_dense(hipStream_t s, int n_f, int npf, int npc, const int* parent,
                           const T* R, const T* xc, T* xf) {
-    k_prolong_dense<T><<<nblk((int64_t)n_f * npf, 256), 256, 0, s>>>(n_f, npf, npc, parent, R,
-                                                                     xc, xf);
+    if (npc <= kMaxTransferModes)
+        k_prolong_dense<T><<<nblk((int64_t)n_f * npf, 256), 256, 0, s>>>(n_f, npf, npc, parent,
+                                                                         R, xc, xf);
+    else
+        k_prolong_rows_wide<T><<<nblk(n_f, 4), 256, 0, s>>>(n_f, npf, npc, parent, R, xc, xf);
 }
 void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
                         double* z) {
@@ -678,14 +796,14 @@ void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const 
 
 #define XDG_INST(T)                                                                           \
     template void launch_spmv<T>(hipStream_t, int, int, int, const int*, const int*, const T*, \
-                                 const T*, const T*, T*, int);                                 \
+                                 const T*, const T*, T*, int, bool);                           \
     template void launch_jacobi<T>(hipStream_t, bool, int, int, const int*, const int*,        \
                                    const int*, const T*, const int64_t*, const T*, const T*,   \
-                                   const T*, T*, T);                                           \
+                                   const T*, T*, T, bool);                                     \
     template void launch_restrict_trunc<T>(hipStream_t, int, int, int, const T*, T*);          \
     template void launch_prolong_trunc<T>(hipStream_t, int, int, int, const T*, T*);           \
-    template void launch_restrict_dense<T>(hipStream_t, int, int, int, const int*, const int*, \
-                                           const T*, const T*, T*);                            \
+    template void launch_restrict_dense<T>(hipStream_t, int, int, int, int, const int*,        \
+                                           const int*, const T*, const T*, T*, T*);            \
     template void launch_prolong_dense<T>(hipStream_t, int, int, int, const int*, const T*,    \
                                           const T*, T*);
 XDG_INST(double)

@@ -133,6 +133,93 @@ __global__ __launch_bounds__(64) void k_galerkin_dense(int n_cblk, int npf, int 
     }
 }
 
+// Large coarse blocks (npc * npc > 32, aggregation levels that keep the fine
+// degree): one 256-thread workgroup per coarse block.  The contributions of
+// one fine row i (consecutive in the list) are summed first,
+// U = sum_l A_il R_l (A_il and R_l staged in LDS kch at a time), then
+// C += R_i^T U: 2 npf^2 npc flops per contribution plus 2 npf npc^2 per fine
+// row, and one round of global loads per kch contributions.  Contributions
+// and rows are added in list order.
+__global__ __launch_bounds__(256) void k_galerkin_dense_lds(int n_cblk, int npf, int npc, int kch,
+                                                           const int* __restrict__ cptr,
+                                                           const int* __restrict__ cfb,
+                                                           const int* __restrict__ crow,
+                                                           const int* __restrict__ ccol,
+                                                           const double* __restrict__ A,
+                                                           const double* __restrict__ R,
+                                                           double* __restrict__ Ac,
+                                                           const int* __restrict__ list) {
+    extern __shared__ double lds[];
+    if ((int)blockIdx.x >= n_cblk) return;
+    const int cb = list ? list[blockIdx.x] : (int)blockIdx.x;
+    const int nf2 = npf * npf, nfc = npf * npc, nc2 = npc * npc;
+    double* sRi = lds;              // row-major npf x npc
+    double* sU = sRi + nfc;         // row-major npf x npc
+    double* sA = sU + nfc;          // kch column-major npf x npf blocks
+    double* sRl = sA + kch * nf2;   // kch row-major npf x npc blocks
+    constexpr int kQ = 5;           // outputs t = threadIdx.x + 256 q (npc, npf <= 35)
+    double cacc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int k0 = cptr[cb], k1 = cptr[cb + 1];
+    int k = k0;
+    while (k < k1) {
+        const int i = crow[k];
+        int kend = k + 1;
+        while (kend < k1 && crow[kend] == i) ++kend;
+        double uacc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int e = threadIdx.x; e < nfc; e += blockDim.x) sRi[e] = R[(int64_t)i * nfc + e];
+        for (int c0 = k; c0 < kend; c0 += kch) {
+            const int nk = min(kch, kend - c0);
+            for (int e = threadIdx.x; e < nk * nf2; e += blockDim.x) {
+                const int kk = e / nf2;
+                sA[e] = A[(int64_t)cfb[c0 + kk] * nf2 + (e - kk * nf2)];
+            }
+            for (int e = threadIdx.x; e < nk * nfc; e += blockDim.x) {
+                const int kk = e / nfc;
+                sRl[e] = R[(int64_t)ccol[c0 + kk] * nfc + (e - kk * nfc)];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {                  // U[a][m2]
+                const int t = threadIdx.x + 256 * q;
+                if (t < nfc) {
+                    const int a = t / npc, m2 = t - a * npc;
+                    double u = 0.0;
+                    for (int kk = 0; kk < nk; ++kk) {
+                        const double* Ak = sA + kk * nf2;
+                        const double* Rk = sRl + kk * nfc;
+                        for (int bb = 0; bb < npf; ++bb) u += Ak[bb * npf + a] * Rk[bb * npc + m2];
+                    }
+                    uacc[q] += u;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int t = threadIdx.x + 256 * q;
+            if (t < nfc) sU[t] = uacc[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {                      // C[m][m2], column-major
+            const int t = threadIdx.x + 256 * q;
+            if (t < nc2) {
+                const int m2 = t / npc, m = t - m2 * npc;
+                double v = 0.0;
+                for (int a = 0; a < npf; ++a) v += sRi[a * npc + m] * sU[a * npc + m2];
+                cacc[q] += v;
+            }
+        }
+        __syncthreads();
+        k = kend;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int t = threadIdx.x + 256 * q;
+        if (t < nc2) Ac[(int64_t)cb * nc2 + t] = cacc[q];
+    }
+}
+
 // D_c (column-major n_c x n_c) from the blocks (i, l) with i, l in cell c;
 // entries not covered by a block stay at the caller's zero fill.
 __global__ __launch_bounds__(256) void k_gather_cells(int n_cells, int np,
@@ -451,9 +538,19 @@ void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const
 void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
                            const int* cfb, const int* crow, const int* ccol, const double* A,
                            const double* R, double* Ac, const int* list) {
-    if (n_cblk > 0)
+    if (n_cblk <= 0) return;
+    if (npc * npc > 32) {
+        // contributions staged per round: as many as 48 KB of LDS allows, at most 4
+        const size_t nfc = (size_t)npf * npc, per = (size_t)npf * npf + nfc;
+        const size_t budget = 48 * 1024 / sizeof(double);
+        const int kch = (int)std::max<size_t>(1, std::min<size_t>(4, (budget - 2 * nfc) / per));
+        const size_t lds = (2 * nfc + (size_t)kch * per) * sizeof(double);
+        k_galerkin_dense_lds<<<n_cblk, 256, lds, s>>>(n_cblk, npf, npc, kch, cptr, cfb, crow,
+                                                      ccol, A, R, Ac, list);
+    } else {
         k_galerkin_dense<<<n_cblk, 64, 0, s>>>(n_cblk, npf, npc, cptr, cfb, crow, ccol, A, R, Ac,
                                                list);
+    }
 }
 void launch_transpose_list(hipStream_t s, int n, const int* list, int np, const double* in,
                            double* out) {

@@ -217,10 +217,10 @@ static void smooth_from_zero(xdg_handle* h, Level& lv, int sweeps) {
         return;
     }
     launch_jacobi<T>(h->s, true, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv), lv.doff,
-                     P<T>::D(lv), b, nullptr, x, om);
+                     P<T>::D(lv), b, nullptr, x, om, lv.next_dir());
     for (int k = 1; k < sweeps; ++k) {
         launch_jacobi<T>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv),
-                         lv.doff, P<T>::D(lv), b, x, y, om);
+                         lv.doff, P<T>::D(lv), b, x, y, om, lv.next_dir());
         std::swap(x, y);
     }
 }
@@ -236,7 +236,7 @@ static void smooth_more(xdg_handle* h, Level& lv, int sweeps) {
     T*& y = P<T>::y(lv);
     for (int k = 0; k < sweeps; ++k) {
         launch_jacobi<T>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv),
-                         lv.doff, P<T>::D(lv), b, x, y, (T)h->opt.omega);
+                         lv.doff, P<T>::D(lv), b, x, y, (T)h->opt.omega, lv.next_dir());
         std::swap(x, y);
     }
 }
@@ -274,12 +274,12 @@ static void vcycle(xdg_handle* h, int l) {
     }
     if (f.t_kind == XDG_T_PTRUNC) {
         launch_spmv<T>(h->s, SPMV_RESID_TRUNC, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f),
-                       P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np);
+                       P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np, f.next_dir());
     } else {
         launch_spmv<T>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f), P<T>::x(f),
-                       P<T>::b(f), P<T>::r(f), 0);
-        launch_restrict_dense<T>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, P<T>::R(f),
-                                 P<T>::r(f), P<T>::b(c));
+                       P<T>::b(f), P<T>::r(f), 0, f.next_dir());
+        launch_restrict_dense<T>(h->s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi,
+                                 P<T>::R(f), P<T>::r(f), P<T>::b(c), P<T>::y(f));
     }
     vcycle<T>(h, l + 1);
     if (f.t_kind == XDG_T_PTRUNC)
@@ -288,6 +288,11 @@ static void vcycle(xdg_handle* h, int l) {
         launch_prolong_dense<T>(h->s, f.n_rows, f.np, c.np, f.parent, P<T>::R(f), P<T>::x(c),
                                 P<T>::x(f));
     smooth_more<T>(h, f, h->opt.nu_post);
+}
+
+// every public call starts its streaming passes in ascending order
+static void reset_dirs(xdg_handle* h) {
+    for (auto& lv : h->L) lv.rev_next = false;
 }
 
 // z = B r for FP64 vectors, using the handle's precision for the cycle
@@ -404,6 +409,7 @@ extern "C" int xdg_vcycle_noalloc(xdg_handle* h, const double* r, double* z) {
     carve_cycle(h, g_scratch[h->dev], ptrs);
     const int nl = (int)h->L.size();
     for (int l = 0; l < nl; ++l) swap_cycle_ptrs(h->L[l], ptrs[l]);     // scratch in
+    reset_dirs(h);
     const int rc = apply_precond(h, r, z);
     for (int l = 0; l < nl; ++l) swap_cycle_ptrs(h->L[l], ptrs[l]);     // handle's back
     return rc;
@@ -461,9 +467,9 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
                 return fail(XDG_EINVAL, w + ": p-truncation needs np_c <= np_f, same rows");
         } else if (tr.kind == XDG_T_DENSE) {
             if (!tr.parent || !tr.R) return fail(XDG_EINVAL, w + ": NULL parent/R");
-            if (tr.np_c > kMaxTransferModes)
+            if (tr.np_c > kMaxDenseCoarse)
                 return fail(XDG_EINVAL, w + ": dense transfer with more than " +
-                                            std::to_string(kMaxTransferModes) + " coarse modes");
+                                            std::to_string(kMaxDenseCoarse) + " coarse modes");
             std::vector<int> cnt(tr.n_rows_c, 0);
             for (int i = 0; i < nr; ++i) {
                 if (tr.parent[i] < 0 || tr.parent[i] >= tr.n_rows_c)
@@ -562,8 +568,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     for (auto& lv : h->L) CHK(setup_vectors(h, lv, h->mixed));
     const int64_t n0 = L0.len();
     CHK(h->alloc(&h->scal, 4096));
-    CHK(h->alloc(&h->part, std::max((size_t)kDotBlocks * 72 * kNrhs,
-                                     (size_t)kDot16Blocks * kMaxBasis16 * kNrhs)));
+    CHK(h->alloc(&h->part, kPartDoubles));
     HIPCHK(hipHostMalloc((void**)&h->h_scal, 4096 * sizeof(double), hipHostMallocDefault));
     CHK(h->alloc(&h->r, n0));
     CHK(h->alloc(&h->z, n0));
@@ -657,9 +662,10 @@ extern "C" int xdg_smooth(xdg_handle* h, int32_t level, const double* b, double*
     if (!b || !x || sweeps < 0) return fail(XDG_EINVAL, "xdg_smooth: bad argument");
     if (h->nrhs == kNrhs) return mrhs_smooth(h, level, b, x, sweeps);
     Level& lv = h->L[level];
+    reset_dirs(h);
     for (int k = 0; k < sweeps; ++k) {
         launch_jacobi<double>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64,
-                              lv.doff, lv.D64, b, x, lv.y64, h->opt.omega);
+                              lv.doff, lv.D64, b, x, lv.y64, h->opt.omega, lv.next_dir());
         HIPCHK(hipMemcpyAsync(x, lv.y64, lv.len() * sizeof(double), hipMemcpyDeviceToDevice,
                               h->s));
     }
@@ -681,7 +687,8 @@ extern "C" int xdg_restrict(xdg_handle* h, int32_t level, const double* rf, doub
     } else if (f.t_kind == XDG_T_PTRUNC)
         launch_restrict_trunc<double>(h->s, f.n_rows, f.np, c.np, rf, rc);
     else
-        launch_restrict_dense<double>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.R64, rf, rc);
+        launch_restrict_dense<double>(h->s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi,
+                                      f.R64, rf, rc, f.y64);
     HIPCHK(hipGetLastError());
     return XDG_OK;
 }
@@ -707,6 +714,7 @@ extern "C" int xdg_prolong(xdg_handle* h, int32_t level, const double* xc, doubl
 extern "C" int xdg_vcycle(xdg_handle* h, const double* r, double* z) {
     if (!h || !r || !z) return fail(XDG_EINVAL, "xdg_vcycle: NULL argument");
     if (h->nrhs == kNrhs) return mrhs_vcycle(h, r, z);
+    reset_dirs(h);
     return apply_precond(h, r, z);
 }
 
@@ -723,7 +731,8 @@ static int read_scalars(xdg_handle* h, int first, int count) {
 
 static int true_relres(xdg_handle* h, const double* b, const double* x, double* out) {
     Level& f = h->L[0];
-    launch_spmv<double>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->w, 0);
+    launch_spmv<double>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->w, 0,
+                        f.next_dir());
     launch_dot(h->s, f.len(), h->w, h->w, h->part, h->scal + S_RR);
     launch_dot(h->s, f.len(), b, b, h->part, h->scal + S_BB);
     CHK(read_scalars(h, S_BB, 2));
@@ -744,7 +753,8 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
     Level& f = h->L[0];
     const int64_t n = f.len();
     hipStream_t s = h->s;
-    launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0);
+    launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0,
+                        f.next_dir());
     launch_dot(s, n, b, b, h->part, h->scal + S_BB);
     launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
     CHK(read_scalars(h, S_BB, 2));
@@ -768,11 +778,18 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
     int cur = S_RZ0, nxt = S_RZ1;
     if (!flex) launch_dot(s, n, h->r, h->z, h->part, h->scal + cur);
     for (int k = 1; k <= h->opt.maxit; ++k) {
-        launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, h->p, nullptr, h->q, 0);
-        launch_dot(s, n, h->p, h->q, h->part, h->scal + S_PQ);
+        // q = A p with p . q formed in the product's epilogue where the block
+        // size allows, and r . r formed in the update of x and r
+        const bool fits = (int64_t)(f.n_rows + 1) / 2 <= (int64_t)kPartDoubles;
+        const bool rev = f.next_dir();
+        if (!fits || !launch_spmv_dot(s, f.n_rows, f.np, f.rp, f.ci, f.A64, h->p, h->q, h->part,
+                                      h->scal + S_PQ, rev)) {
+            launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, h->p, nullptr,
+                                h->q, 0, rev);
+            launch_dot(s, n, h->p, h->q, h->part, h->scal + S_PQ);
+        }
         if (flex) launch_dot(s, n, h->p, h->r, h->part, h->scal + cur);   // alpha numerator
-        launch_cg_update_xr(s, n, h->scal, cur, S_PQ, h->p, h->q, x, h->r);
-        launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
+        launch_cg_update_xr_dot(s, n, h->scal, cur, S_PQ, S_RR, h->p, h->q, x, h->r, h->part);
         CHK(read_scalars(h, S_RR, 2));
         HIPCHK(hipGetLastError());
         *iters = k;
@@ -819,7 +836,8 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
     bool first = true;
     for (;;) {
         // true FP64 residual (the refinement step)
-        launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0);
+        launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0,
+                            f.next_dir());
         launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
         CHK(read_scalars(h, S_RR, 1));
         const double beta = std::sqrt(h->h_scal[S_RR]);
@@ -843,7 +861,8 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
             double* zj = h->Z + (int64_t)j * n;
             double* vn = h->V + (int64_t)(j + 1) * n;
             CHK(apply_precond(h, vj, zj));
-            launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, zj, nullptr, vn, 0);
+            launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, zj, nullptr, vn, 0,
+                                f.next_dir());
             // CGS2
             launch_multidot(s, n, j + 1, h->V, vn, h->part, h->scal + S_H);
             launch_multi_axpy_neg(s, n, j + 1, h->V, h->scal + S_H, vn);
@@ -905,6 +924,7 @@ extern "C" int xdg_solve(xdg_handle* h, const double* b, double* x, double* hist
         return fail(XDG_EINVAL, "xdg_solve: NULL argument");
     *iters = 0;
     int it = 0;
+    reset_dirs(h);
     if (h->nrhs == kNrhs) {
         const int rcm = mrhs_solve(h, b, x, hist, hist_cap, &it, final_relres);
         *iters = it;
@@ -964,6 +984,58 @@ extern "C" int xdg_get_cell_inverse(xdg_handle* h, int32_t level, int32_t cell, 
     HIPCHK(hipStreamSynchronize(h->s));
     for (int r = 0; r < nc; ++r)
         for (int c = 0; c < nc; ++c) out[r * nc + c] = cm[(size_t)c * nc + r];
+    return XDG_OK;
+}
+
+extern "C" int xdg_set_projection(xdg_handle* h, const xdg_projection* P) {
+    if (!h || !P) return fail(XDG_EINVAL, "xdg_set_projection: NULL argument");
+    if (h->nrhs != 1) return fail(XDG_EINVAL, "xdg_set_projection: single-column handles only");
+    const Level& L0 = h->L[0];
+    if (P->n_rows != L0.n_rows || P->np != L0.np || P->n_cols < 1 || P->nnzb < 1 ||
+        !P->row_ptr || !P->col_idx || !P->val)
+        return fail(XDG_EINVAL, "xdg_set_projection: sizes do not match level 0");
+    if (P->row_ptr[0] != 0 || P->row_ptr[P->n_rows] != P->nnzb)
+        return fail(XDG_EINVAL, "xdg_set_projection: row_ptr does not span [0, nnzb]");
+    for (int i = 0; i < P->n_rows; ++i) {
+        if (P->row_ptr[i + 1] < P->row_ptr[i])
+            return fail(XDG_EINVAL, "xdg_set_projection: row_ptr decreases");
+        for (int b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            if (P->col_idx[b] < 0 || P->col_idx[b] >= P->n_cols)
+                return fail(XDG_EINVAL, "xdg_set_projection: column index out of range");
+            if (b > P->row_ptr[i] && P->col_idx[b] <= P->col_idx[b - 1])
+                return fail(XDG_EINVAL, "xdg_set_projection: columns not strictly sorted");
+        }
+    }
+    const size_t nv = (size_t)P->nnzb * P->np * P->np;
+    if (!finite_all(P->val, nv)) return fail(XDG_EINVAL, "xdg_set_projection: non-finite entry");
+    h->release(h->proj_rp);
+    h->release(h->proj_ci);
+    h->release(h->proj_A);
+    h->proj_rp = h->proj_ci = nullptr;
+    h->proj_A = nullptr;
+    h->proj_rows = h->proj_cols = h->proj_nnzb = 0;
+    CHK(h->upload(&h->proj_rp, P->row_ptr, (size_t)P->n_rows + 1));
+    CHK(h->upload(&h->proj_ci, P->col_idx, (size_t)P->nnzb));
+    CHK(h->alloc(&h->proj_A, nv));
+    double* raw = nullptr;
+    CHK(h->upload(&raw, P->val, nv));
+    launch_transpose_blocks<double>(h->s, P->nnzb, P->np, raw, h->proj_A);
+    HIPCHK(hipStreamSynchronize(h->s));
+    h->release(raw);
+    HIPCHK(hipGetLastError());
+    h->proj_rows = P->n_rows;
+    h->proj_cols = P->n_cols;
+    h->proj_nnzb = P->nnzb;
+    return XDG_OK;
+}
+
+extern "C" int xdg_project(xdg_handle* h, const double* x_old, double* x_new) {
+    if (!h || !x_old || !x_new) return fail(XDG_EINVAL, "xdg_project: NULL argument");
+    if (!h->proj_A) return fail(XDG_EINVAL, "xdg_project: no operator (xdg_set_projection)");
+    const Level& L0 = h->L[0];
+    launch_spmv<double>(h->s, SPMV_AX, h->proj_rows, L0.np, h->proj_rp, h->proj_ci, h->proj_A,
+                        x_old, nullptr, x_new, 0);
+    HIPCHK(hipGetLastError());
     return XDG_OK;
 }
 

@@ -64,6 +64,14 @@ struct Level {
     double* Ap64 = nullptr;
     float *bm = nullptr, *xm = nullptr, *ym = nullptr, *rm = nullptr;
     double *bm64 = nullptr, *xm64 = nullptr;
+    // direction of the next streaming pass over this level's blocks
+    // (alternates; reset at every public call so that results are repeatable)
+    bool rev_next = false;
+    bool next_dir() {
+        const bool r = rev_next;
+        rev_next = !r;
+        return r;
+    }
     int64_t len() const { return (int64_t)n_rows * np; }
 };
 
@@ -130,6 +138,11 @@ struct xdg_handle {
     // iterate, its residual, a work vector, and the family size
     std::vector<double*> omZ, omW, omX, omR, omT;
     std::vector<int> om_count;
+    // L2 re-projection from an earlier time level's space (xdg_set_projection):
+    // pattern and column-major blocks on the device
+    int proj_rows = 0, proj_cols = 0, proj_nnzb = 0;
+    int *proj_rp = nullptr, *proj_ci = nullptr;
+    double* proj_A = nullptr;
     float guard = 4.0f;             // |proposal| / |Jacobi step| above this: plain step
     bool learned_ready = false;     // weights and features present
     bool learned_off = false;       // solver-level fallback taken in this solve
@@ -147,6 +160,13 @@ struct xdg_handle {
         }
         allocs.push_back((void*)*ptr);
         return XDG_OK;
+    }
+    // frees one allocation made by alloc()/upload() before the handle ends
+    void release(void* p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        (void)hipFree(p);
     }
     template <typename T>
     int upload(T** ptr, const T* host, size_t n) {

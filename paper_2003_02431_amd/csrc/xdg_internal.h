@@ -17,30 +17,44 @@ namespace xdg {
 
 constexpr int kMaxCell = 88;       // largest smoother cell block order (88^2 FP64 fit 64 KB LDS)
 constexpr int kCoarseNB = 32;      // tile of the blocked coarse inversion
-constexpr int kMaxTransferModes = 8;  // coarse modes of a dense (aggregation) transfer
+constexpr int kMaxTransferModes = 8;  // coarse modes held in registers by the restriction
+constexpr int kMaxDenseCoarse = 35;   // coarse modes of a dense (aggregation) transfer
 
-enum SpmvMode { SPMV_AX = 0, SPMV_RESID = 1, SPMV_RESID_TRUNC = 2 };
+enum SpmvMode { SPMV_AX = 0, SPMV_RESID = 1, SPMV_RESID_TRUNC = 2, SPMV_AX_DOT = 3 };
 
 // ---- level operators (k_level.hip) -------------------------------------
+// rev: visit the block rows (cells) in descending order.  Consecutive
+// streaming passes over one level alternate it, so that each pass starts
+// where the previous one ended, on the blocks still held in the memory-side
+// (Infinity) cache.  Results do not depend on it (rows and cells are
+// independent), except the per-workgroup partials of launch_spmv_dot, which
+// are added in launch order.
 template <typename T>
 void launch_spmv(hipStream_t s, int mode, int n_rows, int np, const int* rp, const int* ci,
-                 const T* A, const T* x, const T* b, T* y, int npc);
+                 const T* A, const T* x, const T* b, T* y, int npc, bool rev = false);
 template <typename T>
 void launch_jacobi(hipStream_t s, bool first, int n_cells, int np, const int* cell_ptr,
                    const int* rp, const int* ci, const T* A, const int64_t* doff, const T* D,
-                   const T* b, const T* xin, T* xout, T omega);
+                   const T* b, const T* xin, T* xout, T omega, bool rev = false);
 template <typename T>
 void launch_restrict_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* rf, T* rc);
 template <typename T>
 void launch_prolong_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* xc, T* xf);
+// rc = R^T rf over the children lists; coarse blocks of more than
+// kMaxTransferModes modes go through tmp (n_f * npc entries: R_i^T rf_i per
+// fine row, then the children sums)
 template <typename T>
-void launch_restrict_dense(hipStream_t s, int n_c, int npf, int npc, const int* child_ptr,
-                           const int* child_idx, const T* R, const T* rf, T* rc);
+void launch_restrict_dense(hipStream_t s, int n_c, int n_f, int npf, int npc,
+                           const int* child_ptr, const int* child_idx, const T* R, const T* rf,
+                           T* rc, T* tmp);
 template <typename T>
 void launch_prolong_dense(hipStream_t s, int n_f, int npf, int npc, const int* parent,
                           const T* R, const T* xc, T* xf);
 void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
                         double* z);
+bool launch_spmv_dot(hipStream_t s, int n_rows, int np, const int* rp, const int* ci,
+                     const double* A, const double* x, double* y, double* partial, double* out,
+                     bool rev = false);
 
 // ---- setup (k_setup.hip) -------------------------------------------------
 template <typename T>
@@ -74,10 +88,20 @@ constexpr int kDotBlocks = 512;
 // basis vectors (restart <= 64); the partial buffer holds both layouts
 constexpr int kDot16Blocks = 2048;
 constexpr int kMaxBasis16 = 64;
+// doubles of the handle's reduction-partial buffer (holds every layout above
+// and one partial per workgroup of the fused product-and-inner-product)
+constexpr size_t kPartDoubles = (size_t)kDot16Blocks * kMaxBasis16 * 16;
 void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial,
                 double* out);
 void launch_cg_update_xr(hipStream_t s, int64_t n, const double* scal, int i_rz, int i_pq,
                          const double* p, const double* q, double* x, double* r);
+// the same update and scal[i_rr] = r . r of the new r (the partial grid and
+// order of launch_dot: the same value bit for bit)
+void launch_cg_update_xr_dot(hipStream_t s, int64_t n, double* scal, int i_rz, int i_pq,
+                             int i_rr, const double* p, const double* q, double* x, double* r,
+                             double* partial);
+// *out = sum of partial[0 .. np-1] in a fixed order
+void launch_dot_final(hipStream_t s, const double* partial, int np, double* out);
 void launch_cg_update_p(hipStream_t s, int64_t n, const double* scal, int i_new, int i_old,
                         const double* z, double* p);
 void launch_fcg_update_p(hipStream_t s, int64_t n, const double* scal, int i_zq, int i_pq,

@@ -20,14 +20,16 @@ def _log(*a):
     sys.stdout.flush()
 
 
-def test_pairs_sampled_64():
+def test_pairs_sampled_64(problem_cache):
     import torch
     from paper_2003_02431_amd import binding as B
     from xdg_inputs import features, problems
     assert torch.cuda.is_available()
     _log("[gpu-fullsize-learned] generating the 64^3 p=3 ellipsoid workload and cell features")
-    pr = problems.c4(seed=0, n=64, p=3, nrhs=1)
-    b = np.asarray(pr.b).reshape(-1)
+    # the 16-column full-size test shares this problem (first right-hand side here)
+    pr = problem_cache(("c4", 0, 64, 3), lambda: problems.c4(seed=0, n=64, p=3, nrhs=16,
+                                                                     verbose=True))
+    b = np.ascontiguousarray(np.asarray(pr.b)[:, 0])
     rs, g = features.cell_features(pr)
     S = B.Solver(pr, B.options(krylov=B.XDG_FGMRES, restart=30, rtol=1e-8, maxit=100))
     B.xdg_set_cell_features(S.h, rs, g)

@@ -1,6 +1,8 @@
-"""The 16-right-hand-side path at full size (64^3 p=3 ellipsoid workload, the
-configuration the multi-RHS benchmark runs), checked on sampled outputs that
-the oracle's definitions give one row or one cell at a time:
+"""The 16-right-hand-side path at full size (64^3 ellipsoid workload at p = 3
+and p = 4, the configurations the multi-RHS benchmark runs; at p = 4 the
+level-0 block arrays hold 1,833,848 x 35^2 = 2.25e9 entries, more than 2^31,
+so every block offset must be 64-bit), checked on sampled outputs that the
+oracle's definitions give one row or one cell at a time:
   * FP64 MFMA block product: sampled rows y_i = sum_b M_ib X_b within 1e-13;
   * FP32 MFMA block product: sampled rows against the same sum over the
     operator and X rounded to FP32, within 1e-6 (the kernel's accumulation);
@@ -23,14 +25,21 @@ def _log(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def case():
+@pytest.fixture(scope="module", params=[3, 4])
+def case(request, problem_cache):
     import torch
     from paper_2003_02431_amd import binding as B
     from xdg_inputs import problems
     assert torch.cuda.is_available()
-    _log("[gpu-fullsize] generating the 64^3 p=3 16-column workload")
-    pr = problems.c4(seed=0, n=64, p=3, nrhs=K)
+    p = request.param
+    _log(f"[gpu-fullsize] generating the 64^3 p={p} 16-column workload")
+    if p == 3:
+        pr = problem_cache(("c4", 0, 64, 3), lambda: problems.c4(seed=0, n=64, p=3, nrhs=K,
+                                                                     verbose=True))
+    else:
+        pr = problems.c4(seed=0, n=64, p=p, nrhs=K, verbose=True)
+        if pr.col_idx.size * pr.np * pr.np <= 2 ** 31:
+            raise AssertionError("the p = 4 case must exceed 2^31 block entries")
     S = B.Solver(pr, B.options(krylov=B.XDG_FGMRES, precision=B.XDG_MIXED, nrhs=K,
                                restart=20, rtol=1e-8, maxit=2000))
     _log(f"[gpu-fullsize] rows={pr.n_rows} nnzb={pr.col_idx.size}")
@@ -56,7 +65,9 @@ def test_spmm_sampled(case):
     L = pr.n_rows * pr.np
     rng = np.random.default_rng(31)
     X = rng.uniform(-1, 1, (L, K))
-    rows = rng.choice(pr.n_rows, 200, replace=False)
+    # random rows plus the last ones (at p = 4 their blocks lie beyond entry 2^31)
+    rows = np.union1d(rng.choice(pr.n_rows - 20, 180, replace=False),
+                      np.arange(pr.n_rows - 20, pr.n_rows))
     for prec, tol in ((B.XDG_FP64, 1e-13), (B.XDG_MIXED, 1e-6)):
         Y = S.vec(0)
         B.xdg_spmm(S.h, 0, prec, S.vec(0, X), Y)
@@ -65,7 +76,7 @@ def test_spmm_sampled(case):
         got = np.concatenate([y[i * pr.np:(i + 1) * pr.np] for i in rows])
         ref = np.concatenate([_row(pr, i, Xr, prec != B.XDG_FP64) for i in rows])
         e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        _log(f"  64^3 spmm precision {prec}: sampled rel err {e:.2e} (tol {tol:g})")
+        _log(f"  64^3 {pr.np} modes spmm precision {prec}: sampled rel err {e:.2e} (tol {tol:g})")
         assert e <= tol
 
 
@@ -83,7 +94,9 @@ def test_smoother_sampled(case):
     r32 = lambda v: np.asarray(v, dtype=np.float32).astype(np.float64)
     b32, x32 = r32(b), r32(x0)
     cp = np.asarray(pr.cell_ptr)
-    cells = rng.choice(len(cp) - 1, 100, replace=False)
+    n_cells = len(cp) - 1
+    cells = np.union1d(rng.choice(n_cells - 10, 90, replace=False),
+                       np.arange(n_cells - 10, n_cells))
     worst = 0.0
     for c in cells:
         rows = np.arange(cp[c], cp[c + 1])
@@ -113,5 +126,6 @@ def test_smoother_sampled(case):
         dy = n * U32 * (abs(Dinv) @ abs(r)) + abs(Dinv) @ dr
         dx = U32 * (abs(ref) + 0.7 * abs(y)) + 0.7 * dy
         worst = max(worst, float(np.max(abs(xg[idx] - ref) / np.maximum(dx, 1e-300))))
-    _log(f"  64^3 MFMA smoother: 100 sampled cells, worst |err| / bound {worst:.2e}")
+    _log(f"  64^3 p={pr.np} modes MFMA smoother: {cells.size} sampled cells, worst |err| / bound "
+         f"{worst:.2e}")
     assert worst <= 1.0

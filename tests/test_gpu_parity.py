@@ -43,6 +43,11 @@ def _make(name):
         return problems.c2(seed=3, n=8, hier=[("p", 1), ("h", 1)])
     if name == "c2n16":
         return problems.c2(seed=1, n=16)
+    if name == "c2n8hp":
+        # aggregation level at the fine degree (20 coarse modes per block)
+        return problems.c2(seed=4, n=8, hier=problems.hierarchy("hp", 8, 3))
+    if name == "c2n16h3p1":
+        return problems.c2(seed=2, n=16, hier=problems.hierarchy("h3p1", 16, 3))
     if name == "c4n8p4":
         # p = 4 (35 modes per block: the one-row-per-lane stream), ellipsoid
         pr = problems.c4(seed=5, n=8, p=4, nrhs=1)
@@ -66,7 +71,7 @@ def _case(name, torch):
     return _STATE[name]
 
 
-CASES = ["c1", "c2n8", "c2n16", "c4n8p4"]
+CASES = ["c1", "c2n8", "c2n16", "c4n8p4", "c2n8hp", "c2n16h3p1"]
 
 
 def _rel(a, b):
@@ -464,7 +469,7 @@ def test_full_size_sampled(torch):
     from paper_2003_02431_amd import binding as B
     from xdg_inputs import problems
     _log("[gpu-parity] generating 32^3 p=3 workload")
-    pr = problems.c2(seed=0, n=32)
+    pr = problems.c2(seed=0, n=32, verbose=True)
     A = mg.block_matrix(pr.row_ptr, pr.col_idx, pr.val)
     S = B.Solver(pr, B.options(rtol=1e-10, maxit=600))
     rng = np.random.default_rng(15)

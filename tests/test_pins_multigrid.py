@@ -31,9 +31,22 @@ def _p3d(n=4, p=2):
                  q_cut=10)
 
 
+def _p3d_same_degree(n=4, p=2):
+    """Aggregation level at the fine degree (the paper's sequence keeps the
+    degree on every level): 4^3 p2 -> 2^3 aggregates p2."""
+    return build("mg3dh", 3, n, p, Quadric.sphere([0.02, -0.03, 0.01], 0.6), (1.0, 1000.0),
+                 hierarchy=[("h", 1, p)], rhs="random", rng=np.random.default_rng(5),
+                 q_cut=10)
+
+
 @pytest.fixture(scope="module")
 def pr2():
     return _p2d()
+
+
+@pytest.fixture(scope="module")
+def pr3h():
+    return _p3d_same_degree()
 
 
 @pytest.fixture(scope="module")
@@ -51,19 +64,19 @@ def _gram(geom, level, r, q):
     return G
 
 
-def test_bases_orthonormal(pr2, pr3):
+def test_bases_orthonormal(pr2, pr3, pr3h):
     """Mass matrix of every part is the identity, to the rounding of a
     Cholesky re-orthonormalisation (kappa(G) eps with kappa(G) up to ~1e4 on
     small cut parts inside a large bounding box)."""
-    for pr in (pr2, pr3):
+    for pr in (pr2, pr3, pr3h):
         for lv in pr.levels:
             worst = max(np.abs(_gram(pr.geom, lv, r, lv.deg + 2) - np.eye(lv.np)).max()
                         for r in range(lv.n_rows))
             assert worst < 1e-10
 
 
-def test_transfer_invariants(pr2, pr3):
-    for pr in (pr2, pr3):
+def test_transfer_invariants(pr2, pr3, pr3h):
+    for pr in (pr2, pr3, pr3h):
         for t, (fine, coarse) in enumerate(zip(pr.levels[:-1], pr.levels[1:])):
             T = pr.transfers[t]
             if T["kind"] == mg.T_PTRUNC:
@@ -89,10 +102,10 @@ def test_transfer_invariants(pr2, pr3):
                 assert np.allclose(Rm.T @ Rm, np.eye(Rm.shape[1]), atol=1e-12)
 
 
-def test_galerkin_equals_coarse_assembly(pr2, pr3):
+def test_galerkin_equals_coarse_assembly(pr2, pr3, pr3h):
     """R^T M R equals SIP assembled on the coarse space with the fine-level
     penalties; faces inside a coarse aggregate drop out."""
-    for pr in (pr2, pr3):
+    for pr in (pr2, pr3, pr3h):
         H = mg.hierarchy_of(pr)
         for l in range(1, H.nlev):
             lv = pr.levels[l]
@@ -124,8 +137,8 @@ def _vcycle_dense(H, level):
     return (I - E) @ np.linalg.inv(A)
 
 
-def test_vcycle_closed_form_and_spd(pr2, pr3):
-    for pr in (pr2, pr3):
+def test_vcycle_closed_form_and_spd(pr2, pr3, pr3h):
+    for pr in (pr2, pr3, pr3h):
         H = mg.hierarchy_of(pr)
         L = H.A[0].shape[0]
         B = np.column_stack([H.vcycle(e) for e in np.eye(L)])
@@ -170,9 +183,9 @@ def test_jacobi_single_block_is_exact():
     assert np.allclose(A @ x, b, atol=1e-13)
 
 
-@pytest.mark.parametrize("which", ["2d", "3d"])
-def test_mg_pcg_matches_dense_direct(which, pr2, pr3):
-    pr = pr2 if which == "2d" else pr3
+@pytest.mark.parametrize("which", ["2d", "3d", "3d-same-degree"])
+def test_mg_pcg_matches_dense_direct(which, pr2, pr3, pr3h):
+    pr = {"2d": pr2, "3d": pr3, "3d-same-degree": pr3h}[which]
     H = mg.hierarchy_of(pr)
     A = H.A[0].toarray()
     xd = np.linalg.solve(A, pr.b)

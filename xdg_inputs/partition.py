@@ -27,12 +27,15 @@ from scipy.sparse.csgraph import connected_components
 from .basis import BoxBasis, PartBasis, n_modes, orthonormalize
 
 
-def alpha_edges(geom, alpha):
-    """Edges (part_u, part_v), part = 2*j + s, of the agglomeration map."""
+def alpha_edges(geom, alpha, force=None):
+    """Edges (part_u, part_v), part = 2*j + s, of the agglomeration map.
+    force: parts (j, s) that must be agglomerated whatever their volume
+    fraction (cut parts that are new at this time level, Section 2.3)."""
     edges = []
+    force = force or set()
     for j in sorted(geom.cut):
         for s in range(2):
-            if not geom.present[j, s] or geom.frac[j, s] > alpha:
+            if not geom.present[j, s] or (geom.frac[j, s] > alpha and (j, s) not in force):
                 continue
             best, best_vol = -1, -1.0
             for d, plane, t, sg in geom.cell_faces(j):

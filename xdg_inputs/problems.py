@@ -43,21 +43,28 @@ class Problem:
 
 def build(name, D, n, p, phi, mu, alpha=0.1, hierarchy=(), rhs="random", nrhs=1,
           rng=None, f=None, g_dir=None, q_cut=None, q_std=None, c_eta=C_ETA_DEFAULT,
-          verbose=False):
+          verbose=False, force_agglomerate=None):
     """Generate one problem.  `hierarchy` lists the coarse levels in order as
-    ("p", degree) for a p-level on the same aggregates or ("h", m) for the
-    2^m-blocking aggregation level at degree 1."""
+    ("p", degree) for a p-level on the same aggregates, ("h", m) for the
+    2^m-blocking aggregation level at degree 1, or ("h", m, degree) for that
+    level at another degree (the paper's aggregation sequence keeps the
+    degree of the fine level)."""
     t0 = time.time()
     q_cut = q_cut or max(2 * p + 4, 8)
     q_std = q_std or p + 2
     geom = Geometry(D, n, phi, q_cut)
-    a_edges = alpha_edges(geom, alpha)
+    force = force_agglomerate(geom) if force_agglomerate else None
+    a_edges = alpha_edges(geom, alpha, force)
     L0 = Level(geom, 0, p, level_labels(geom, a_edges, 0))
     L0.build_bases(q_std)
     pen = compute_penalty(geom, L0, c_eta)
     t1 = time.time()
+    if verbose:
+        print(f"[{name}] geometry, agglomeration and bases: {t1 - t0:.1f}s", flush=True)
     row_ptr, col_idx, val = assemble(geom, L0, mu, pen, q_std)
     t2 = time.time()
+    if verbose:
+        print(f"[{name}] assembly: {t2 - t1:.1f}s", flush=True)
     pr = Problem()
     pr.name, pr.D, pr.n, pr.p, pr.np = name, D, n, p, L0.np
     pr.mu, pr.alpha, pr.c_eta = tuple(mu), alpha, c_eta
@@ -72,7 +79,7 @@ def build(name, D, n, p, phi, mu, alpha=0.1, hierarchy=(), rhs="random", nrhs=1,
     # transfers
     pr.transfers = []
     fine = L0
-    for kind, arg in hierarchy:
+    for kind, arg, *deg_h in hierarchy:
         if kind == "p":
             lv = Level.__new__(Level)
             lv.__dict__.update({k: v for k, v in fine.__dict__.items() if k != "bases"})
@@ -83,7 +90,7 @@ def build(name, D, n, p, phi, mu, alpha=0.1, hierarchy=(), rhs="random", nrhs=1,
                                      parent=np.arange(fine.n_rows, dtype=np.int32), R=None,
                                      cell_ptr_c=lv.cell_ptr.astype(np.int32)))
         else:
-            deg = 1 if fine.deg >= 1 else 0
+            deg = deg_h[0] if deg_h else (1 if fine.deg >= 1 else 0)
             lv = Level(geom, arg, deg, level_labels(geom, a_edges, arg))
             lv.build_bases(max(deg + 1, 2))
             parent, R = dense_transfer(fine, lv, max(fine.deg + 1, 2))
@@ -118,11 +125,32 @@ def c1(n=16, p=2):
                  hierarchy=hier, rhs="load", f=f, g_dir=lambda X, s: np.zeros(len(X)))
 
 
+def hierarchy(kind, n, p):
+    """Named coarse-level sequences of the 3D workloads (n a power of 2):
+      "p1h"   p -> p1 on the fine aggregates, then aggregation levels at p1 down
+              to the 8^3 blocking (4 levels at 32^3);
+      "h3p1"  one aggregation level at the fine degree (2^3 blocking), then p1
+              on it, then aggregation levels at p1 down to 8^3 (4 levels at 32^3);
+      "hp"    aggregation levels at the fine degree down to the 4^3 blocking
+              (the paper's sequence: the degree is kept on every level);
+      "h2p"   aggregation levels at the fine degree down to the 8^3 blocking,
+              then p1 on it (4 levels at 32^3, the coarsest of "p1h")."""
+    L = int(np.log2(n))
+    if kind == "h2p":
+        return [("h", m, p) for m in range(1, L - 2)] + [("p", 1)]
+    if kind == "p1h":
+        return [("p", 1)] + [("h", m) for m in range(1, L - 2)]
+    if kind == "h3p1":
+        return [("h", 1, p), ("p", 1)] + [("h", m) for m in range(2, L - 2)]
+    if kind == "hp":
+        return [("h", m, p) for m in range(1, L - 1)]
+    raise KeyError(kind)
+
+
 def c2(seed=0, n=32, p=3, verbose=False, hier=None):
     g = _rng.problem_rng(seed)
     ctr = _rng.sphere_jitter(g, 0.05)
-    nh = int(np.log2(n)) - 3          # h-levels down to the 8^3 aggregation
-    hier = hier or [("p", 1)] + [("h", m) for m in range(1, nh + 1)]
+    hier = hier or hierarchy("p1h", n, p)
     return build(f"c2_3d_p{p}_n{n}_s{seed}", 3, n, p, Quadric.sphere(ctr, 0.6), (1.0, 1000.0),
                  hierarchy=hier, rhs="random", rng=g, verbose=verbose)
 
@@ -134,6 +162,18 @@ def c4(seed=0, n=64, p=3, nrhs=16, verbose=False):
     hier = [("p", 1)] + [("h", m) for m in range(1, nh + 1)]
     return build(f"c4_3d_p{p}_n{n}_s{seed}", 3, n, p, Quadric.ellipsoid([0.0, 0.0, 0.0], axes),
                  (1.0, 1000.0), hierarchy=hier, rhs="random", nrhs=nrhs, rng=g, verbose=verbose)
+
+
+def paper(n=16, p=3, hier=None, c_eta=C_ETA_DEFAULT, verbose=False):
+    """The Section 4 workload: sphere of radius 0.7 at the origin in (-1,1)^3,
+    mu 1 inside | 1000 outside, f = 1, homogeneous Dirichlet data, alpha = 0.1.
+    Default hierarchy: aggregation levels at the fine degree down to 4^3
+    (the paper's multigrid keeps the degree on every level)."""
+    nh = int(np.log2(n)) - 2
+    hier = hier if hier is not None else [("h", m, p) for m in range(1, nh + 1)]
+    return build(f"paper_3d_p{p}_n{n}", 3, n, p, Quadric.sphere([0.0, 0.0, 0.0], 0.7),
+                 (1.0, 1000.0), hierarchy=hier, rhs="load", f=lambda X, s: np.ones(len(X)),
+                 g_dir=lambda X, s: np.zeros(len(X)), c_eta=c_eta, verbose=verbose)
 
 
 def paper_sphere_fractions(n, alpha=0.1):
