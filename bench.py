@@ -3,7 +3,9 @@
 Workload: 3D SIP Poisson, p = 3 (20 modes/species/cell), 32^3 cut grid on
 [-1,1]^3, sphere r = 0.6 with seeded centre jitter, diffusivity 1 | 1000,
 alpha = 0.1, RHS ~ U[-1,1] per coefficient, 4-level aggregation + p multigrid
-V-cycle with damped block Jacobi (2 pre / 2 post, omega 0.7), FP64 CG.
+V-cycle (p3 -> p1 -> 16^3 -> 8^3 aggregates) with damped block Jacobi (1 pre /
+1 post, omega 0.9: the fastest measured setting; 2 / 2 at omega 0.7 is
+--nu 2 --omega 0.7), FP64 CG.
 
 One step = the whole hot path on device-resident input: numeric hierarchy
 set-up from the level-0 values (Galerkin products, cell-block and coarsest
@@ -67,7 +69,7 @@ def time_spmv(torch, B, S, level, reps=50):
     return e0.elapsed_time(e1) / reps * 1e-3   # seconds per launch
 
 
-def cpu_baseline(pr):
+def cpu_baseline(pr, omega=0.7, nu=2):
     """The plain-loop C++17/OpenMP oracle as it stands, on every host core:
     its hierarchy set-up (Galerkin products, Cholesky cell-block and coarsest
     factorisations) plus its PCG solve of the same problem to rel.res 1e-8,
@@ -79,7 +81,7 @@ def cpu_baseline(pr):
         mg_omp.build()
     cores = mg_omp.threads()
     t0 = time.perf_counter()
-    O = mg_omp.OmpHierarchy(pr)
+    O = mg_omp.OmpHierarchy(pr, omega=omega, nu=nu)
     t1 = time.perf_counter()
     x8, _, it8 = O.pcg(pr.b, rtol=1e-8, maxit=2000)
     t2 = time.perf_counter()
@@ -355,7 +357,8 @@ def bench_moving(args):
                                hierarchy=problems.hierarchy(args.hier, args.n, 3), verbose=True)
     log(f"[bench-moving] two time levels generated in {time.time() - t0:.1f}s: rows "
         f"{pr0.n_rows} -> {pr1.n_rows}")
-    opt = B.options(krylov=B.XDG_CG, rtol=1e-8, maxit=1000)
+    opt = B.options(krylov=B.XDG_CG, rtol=1e-8, maxit=1000, nu_pre=args.nu, nu_post=args.nu,
+                    omega=args.omega)
     S0 = B.Solver(pr0, opt)
     x0 = S0.vec(0)
     B.xdg_solve(S0.h, S0.vec(0, pr0.b), x0)
@@ -392,7 +395,8 @@ def bench_moving(args):
            "value": round(float(med.sum()), 5), "unit": "s", "higher_is_better": False,
            "config": {"workload": f"xdg_sip_poisson_3d_p3_{args.n}^3_moving_sphere_r0.6",
                       "rows_t0": int(pr0.n_rows), "rows_t1": int(pr1.n_rows),
-                      "nnzb_t1": int(pr1.col_idx.size), "hierarchy": args.hier},
+                      "nnzb_t1": int(pr1.col_idx.size), "hierarchy": args.hier,
+                      "smoother": f"block-Jacobi {args.nu}+{args.nu} omega={args.omega}"},
            "create_s": round(float(med[0]), 5), "operator_upload_s": round(float(med[1]), 5),
            "projection_s": round(float(med[2]), 6), "solve_s": round(float(med[3]), 5),
            "iters_from_projection": rows[-1][4], "iters_from_zero": rows[-1][5],
@@ -414,6 +418,9 @@ def main():
                          "c4: 64^3 cut grid with 16 right-hand sides; "
                          "c5: 64^3 p=3 with the learned smoother")
     ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--nu", type=int, default=1,
+                    help="block-Jacobi sweeps before and after the coarse correction")
+    ap.add_argument("--omega", type=float, default=0.9, help="Jacobi damping")
     ap.add_argument("--hier", default="p1h", choices=["p1h", "h3p1", "hp", "h2p"],
                     help="coarse-level sequence of the 32^3 workload (xdg_inputs.problems."
                          "hierarchy)")
@@ -450,7 +457,10 @@ def main():
     pr = load_problem(args.n, args.seed, hier=args.hier)
     log(f"[bench] generated rows={pr.n_rows} nnzb={pr.col_idx.size} in {time.time() - t0:.1f}s")
 
-    opt8 = B.options(krylov=B.XDG_CG, rtol=1e-8, maxit=1000)
+    def opts(**kw):
+        return B.options(nu_pre=args.nu, nu_post=args.nu, omega=args.omega, **kw)
+
+    opt8 = opts(krylov=B.XDG_CG, rtol=1e-8, maxit=1000)
     S = B.Solver(pr, opt8)
     log(f"[bench] handle created, set-up {B.xdg_setup_time(S.h):.1f} ms")
     if args.profile_spmv:
@@ -478,7 +488,7 @@ def main():
         return
 
     if args.profile_mixed:
-        Sc = B.Solver(pr, B.options(krylov=B.XDG_CG, precision=B.XDG_MIXED, rtol=1e-8,
+        Sc = B.Solver(pr, opts(krylov=B.XDG_CG, precision=B.XDG_MIXED, rtol=1e-8,
                                     maxit=1000))
         b_dev = Sc.vec(0, pr.b)
         for _ in range(2):
@@ -518,7 +528,7 @@ def main():
     setup_ms = B.xdg_setup_time(S.h)
 
     # time to 1e-10 (config's own tolerance) and the iterate error of the 1e-8 stop
-    S10 = B.Solver(pr, B.options(krylov=B.XDG_CG, rtol=1e-10, maxit=1000))
+    S10 = B.Solver(pr, opts(krylov=B.XDG_CG, rtol=1e-10, maxit=1000))
     x10 = S10.vec(0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -532,7 +542,7 @@ def main():
 
     mixed = None
     if not args.no_mixed:
-        Sm = B.Solver(pr, B.options(krylov=B.XDG_FGMRES, restart=30, precision=B.XDG_MIXED,
+        Sm = B.Solver(pr, opts(krylov=B.XDG_FGMRES, restart=30, precision=B.XDG_MIXED,
                                     rtol=1e-8, maxit=1000))
         xm = Sm.vec(0)
         B.xdg_update_matrix(Sm.h, val_dev)
@@ -562,7 +572,7 @@ def main():
         keep["fgmres_1e-10"] = xm.clone()
         Sm.close()
         # FP32 V-cycle inside flexible CG to rel.res 1e-8
-        Sc = B.Solver(pr, B.options(krylov=B.XDG_CG, precision=B.XDG_MIXED, rtol=1e-8,
+        Sc = B.Solver(pr, opts(krylov=B.XDG_CG, precision=B.XDG_MIXED, rtol=1e-8,
                                     maxit=1000))
         xc = Sc.vec(0)
         B.xdg_update_matrix(Sc.h, val_dev)
@@ -594,7 +604,7 @@ def main():
             f"to rel.res 1e-10: {te} iters {ite}")
 
     # the paper's orthonormalisation multigrid as the solver (FP64)
-    So = B.Solver(pr, B.options(krylov=B.XDG_ORTHOMG, restart=30, rtol=1e-8, maxit=1000))
+    So = B.Solver(pr, opts(krylov=B.XDG_ORTHOMG, restart=30, rtol=1e-8, maxit=1000))
     xo = So.vec(0)
     B.xdg_update_matrix(So.h, val_dev)
     B.xdg_solve(So.h, b_dev, xo, hist_cap=2000)         # warm-up
@@ -653,7 +663,7 @@ def main():
     cpu, errs = None, {}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: the C++ oracle's set-up and PCG solve to rel.res 1e-8")
-        cpu, xstar, it_star = cpu_baseline(pr)
+        cpu, xstar, it_star = cpu_baseline(pr, omega=args.omega, nu=args.nu)
         log(f"[bench] cpu baseline {cpu}")
         xs_dev = torch.as_tensor(xstar).cuda()
         ns = torch.linalg.norm(xs_dev)
@@ -681,8 +691,12 @@ def main():
         "config": {"workload": f"xdg_sip_poisson_3d_p3_{args.n}^3_sphere_r0.6_mu1:1000",
                    "block_rows": int(pr.n_rows), "np": int(pr.np),
                    "nnzb": int(pr.col_idx.size), "dofs": int(pr.n_rows * pr.np),
-                   "levels": len(pr.transfers) + 1, "krylov": "CG", "smoother":
-                   "block-Jacobi 2+2 omega=0.7", "seed": args.seed},
+                   "levels": len(pr.transfers) + 1, "hierarchy": args.hier,
+                   "level_dofs": [int(pr.n_rows * pr.np)] + [int(T["n_rows_c"] * T["np_c"])
+                                                             for T in pr.transfers],
+                   "krylov": "CG",
+                   "smoother": f"block-Jacobi {args.nu}+{args.nu} omega={args.omega}",
+                   "seed": args.seed},
         "iters_to_1e-8": int(np.median(its)),
         "setup_ms": round(setup_ms, 3),
         "time_to_1e-10_s": round(dt10, 6),

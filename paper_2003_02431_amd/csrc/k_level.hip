@@ -527,6 +527,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_restrict_dense(int n_c, int npf, int npc,
                                                         const int* __restrict__ child_ptr,
                                                         const int* __restrict__ child_idx,
+                                                        const int* __restrict__ ridx,
                                                         const T* __restrict__ R,
                                                         const T* __restrict__ rf,
                                                         T* __restrict__ rc) {
@@ -541,7 +542,7 @@ __global__ __launch_bounds__(256) void k_restrict_dense(int n_c, int npf, int np
         const int k = t / npf, a = t - k * npf;
         const int i = child_idx[k0 + k];
         const T rv = rf[(int64_t)i * npf + a];
-        const T* Ri = R + ((int64_t)i * npf + a) * npc;
+        const T* Ri = R + ((int64_t)ridx[i] * npf + a) * npc;
 #pragma unroll
         for (int m = 0; m < kMaxTransferModes; ++m)
             if (m < npc) acc[m] += Ri[m] * rv;
@@ -565,6 +566,7 @@ __global__ __launch_bounds__(256) void k_restrict_dense(int n_c, int npf, int np
 //     tree over the groups;
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict_rows_wide(int n_f, int npf, int npc,
+                                                            const int* __restrict__ ridx,
                                                             const T* __restrict__ R,
                                                             const T* __restrict__ rf,
                                                             T* __restrict__ t) {
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(256) void k_restrict_rows_wide(int n_f, int npf, in
     if (i >= n_f) return;
     const int G = 64 / npc;
     const int m = lane % npc, g = lane / npc;
-    const T* Ri = R + (int64_t)i * npf * npc;
+    const T* Ri = R + (int64_t)ridx[i] * npf * npc;
     const T* ri = rf + (int64_t)i * npf;
     T acc = 0;
     if (g < G)
@@ -606,6 +608,7 @@ __global__ void k_restrict_children(int n_c, int npc, const int* __restrict__ ch
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_rows_wide(int n_f, int npf, int npc,
                                                            const int* __restrict__ parent,
+                                                           const int* __restrict__ ridx,
                                                            const T* __restrict__ R,
                                                            const T* __restrict__ xc,
                                                            T* __restrict__ xf) {
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(256) void k_prolong_rows_wide(int n_f, int npf, int
     if (i >= n_f) return;
     const int G = 64 / npc;
     const int m = lane % npc, g = lane / npc;
-    const T* Ri = R + (int64_t)i * npf * npc;
+    const T* Ri = R + (int64_t)ridx[i] * npf * npc;
     const T xm = g < G ? xc[(int64_t)parent[i] * npc + m] : T(0);
     const int steps = (npf + G - 1) / G;
     for (int k = 0; k < steps; ++k) {
@@ -631,13 +634,14 @@ __global__ __launch_bounds__(256) void k_prolong_rows_wide(int n_f, int npf, int
 // xf[i][a] += sum_m R_i[a][m] xc[parent(i)][m]
 template <typename T>
 __global__ void k_prolong_dense(int n_f, int npf, int npc, const int* __restrict__ parent,
+                                const int* __restrict__ ridx,
                                 const T* __restrict__ R, const T* __restrict__ xc,
                                 T* __restrict__ xf) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n_f * npf) return;
     const int i = (int)(t / npf);
     const int a = (int)(t - (int64_t)i * npf);
-    const T* Ri = R + (int64_t)i * npf * npc + a * npc;
+    const T* Ri = R + (int64_t)ridx[i] * npf * npc + a * npc;
     const T* xp = xc + (int64_t)parent[i] * npc;
     T acc = 0;
     for (int m = 0; m < npc; ++m) acc += Ri[m] * xp[m];
@@ -771,23 +775,26 @@ void launch_prolong_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* 
 }
 template <typename T>
 void launch_restrict_dense(hipStream_t s, int n_c, int n_f, int npf, int npc, const int* cptr,
-                           const int* cidx, const T* R, const T* rf, T* rc, T* tmp) {
+                           const int* cidx, const int* ridx, const T* R, const T* rf, T* rc,
+                           T* tmp) {
     if (npc <= kMaxTransferModes) {
-        k_restrict_dense<T><<<nblk(n_c, 4), 256, 0, s>>>(n_c, npf, npc, cptr, cidx, R, rf, rc);
+        k_restrict_dense<T><<<nblk(n_c, 4), 256, 0, s>>>(n_c, npf, npc, cptr, cidx, ridx, R, rf,
+                                                          rc);
         return;
     }
-    k_restrict_rows_wide<T><<<nblk(n_f, 4), 256, 0, s>>>(n_f, npf, npc, R, rf, tmp);
+    k_restrict_rows_wide<T><<<nblk(n_f, 4), 256, 0, s>>>(n_f, npf, npc, ridx, R, rf, tmp);
     k_restrict_children<T><<<nblk((int64_t)n_c * npc, 256), 256, 0, s>>>(n_c, npc, cptr, cidx,
                                                                           tmp, rc);
 }
 template <typename T>
 void launch_prolong_dense(hipStream_t s, int n_f, int npf, int npc, const int* parent,
-                          const T* R, const T* xc, T* xf) {
+                          const int* ridx, const T* R, const T* xc, T* xf) {
     if (npc <= kMaxTransferModes)
         k_prolong_dense<T><<<nblk((int64_t)n_f * npf, 256), 256, 0, s>>>(n_f, npf, npc, parent,
-                                                                         R, xc, xf);
+                                                                         ridx, R, xc, xf);
     else
-        k_prolong_rows_wide<T><<<nblk(n_f, 4), 256, 0, s>>>(n_f, npf, npc, parent, R, xc, xf);
+        k_prolong_rows_wide<T><<<nblk(n_f, 4), 256, 0, s>>>(n_f, npf, npc, parent, ridx, R, xc,
+                                                            xf);
 }
 void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
                         double* z) {
@@ -803,9 +810,10 @@ void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const 
     template void launch_restrict_trunc<T>(hipStream_t, int, int, int, const T*, T*);          \
     template void launch_prolong_trunc<T>(hipStream_t, int, int, int, const T*, T*);           \
     template void launch_restrict_dense<T>(hipStream_t, int, int, int, int, const int*,        \
-                                           const int*, const T*, const T*, T*, T*);            \
-    template void launch_prolong_dense<T>(hipStream_t, int, int, int, const int*, const T*,    \
-                                          const T*, T*);
+                                           const int*, const int*, const T*, const T*, T*,     \
+                                           T*);                                                \
+    template void launch_prolong_dense<T>(hipStream_t, int, int, int, const int*, const int*,  \
+                                          const T*, const T*, T*);
 XDG_INST(double)
 XDG_INST(float)
 #undef XDG_INST

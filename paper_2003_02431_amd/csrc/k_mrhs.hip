@@ -320,7 +320,8 @@ __global__ void k_restrict_trunc_m(int n_rows, int npf, int npc, const T* __rest
 // rc[c][m][k] = sum_{i in children(c)} sum_a R_i[a][m] rf[i][a][k]
 template <typename T>
 __global__ void k_restrict_dense_m(int n_c, int npf, int npc, const int* __restrict__ child_ptr,
-                                   const int* __restrict__ child_idx, const T* __restrict__ R,
+                                   const int* __restrict__ child_idx,
+                                   const int* __restrict__ ridx, const T* __restrict__ R,
                                    const T* __restrict__ rf, T* __restrict__ rc) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n_c * npc * 16) return;
@@ -330,7 +331,7 @@ __global__ void k_restrict_dense_m(int n_c, int npf, int npc, const int* __restr
     T acc = 0;
     for (int q = child_ptr[c]; q < child_ptr[c + 1]; ++q) {
         const int i = child_idx[q];
-        const T* Ri = R + (int64_t)i * npf * npc;
+        const T* Ri = R + (int64_t)ridx[i] * npf * npc;
         const T* ri = rf + (int64_t)i * npf * 16 + k;
         for (int a = 0; a < npf; ++a) acc += Ri[a * npc + m] * ri[a * 16];
     }
@@ -340,6 +341,7 @@ __global__ void k_restrict_dense_m(int n_c, int npf, int npc, const int* __restr
 // xf[i][a][k] += sum_m R_i[a][m] xc[parent(i)][m][k]
 template <typename T>
 __global__ void k_prolong_dense_m(int n_f, int npf, int npc, const int* __restrict__ parent,
+                                  const int* __restrict__ ridx,
                                   const T* __restrict__ R, const T* __restrict__ xc,
                                   T* __restrict__ xf) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -347,7 +349,7 @@ __global__ void k_prolong_dense_m(int n_f, int npf, int npc, const int* __restri
     const int i = (int)(t / (npf * 16));
     const int rem = (int)(t - (int64_t)i * npf * 16);
     const int a = rem >> 4, k = rem & 15;
-    const T* Ri = R + ((int64_t)i * npf + a) * npc;
+    const T* Ri = R + ((int64_t)ridx[i] * npf + a) * npc;
     const T* xp = xc + (int64_t)parent[i] * npc * 16 + k;
     T acc = 0;
     for (int m = 0; m < npc; ++m) acc += Ri[m] * xp[m * 16];
@@ -441,15 +443,16 @@ void launch_restrict_trunc_m(hipStream_t s, int n_rows, int npf, int npc, const 
 }
 template <typename T>
 void launch_restrict_dense_m(hipStream_t s, int n_c, int npf, int npc, const int* cptr,
-                             const int* cidx, const T* R, const T* rf, T* rc) {
+                             const int* cidx, const int* ridx, const T* R, const T* rf, T* rc) {
     k_restrict_dense_m<T><<<nb_((int64_t)n_c * npc * 16, 256), 256, 0, s>>>(n_c, npf, npc, cptr,
-                                                                            cidx, R, rf, rc);
+                                                                            cidx, ridx, R, rf,
+                                                                            rc);
 }
 template <typename T>
 void launch_prolong_dense_m(hipStream_t s, int n_f, int npf, int npc, const int* parent,
-                            const T* R, const T* xc, T* xf) {
-    k_prolong_dense_m<T><<<nb_((int64_t)n_f * npf * 16, 256), 256, 0, s>>>(n_f, npf, npc, parent, R,
-                                                                           xc, xf);
+                            const int* ridx, const T* R, const T* xc, T* xf) {
+    k_prolong_dense_m<T><<<nb_((int64_t)n_f * npf * 16, 256), 256, 0, s>>>(n_f, npf, npc, parent,
+                                                                           ridx, R, xc, xf);
 }
 void launch_coarse_gemm16(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
                           double* z) {
@@ -468,15 +471,15 @@ template void launch_pack_blocks<float>(hipStream_t, int64_t, int, const double*
 template void launch_pack_blocks<double>(hipStream_t, int64_t, int, const double*, double*);
 template void launch_prolong_trunc_m<float>(hipStream_t, int, int, int, const float*, float*);
 template void launch_restrict_dense_m<float>(hipStream_t, int, int, int, const int*, const int*,
-                                             const float*, const float*, float*);
-template void launch_prolong_dense_m<float>(hipStream_t, int, int, int, const int*, const float*,
-                                            const float*, float*);
+                                             const int*, const float*, const float*, float*);
+template void launch_prolong_dense_m<float>(hipStream_t, int, int, int, const int*, const int*,
+                                            const float*, const float*, float*);
 // FP64 forms: the boundary's restriction / prolongation on 16-column vectors
 template void launch_restrict_trunc_m<double>(hipStream_t, int, int, int, const double*, double*);
 template void launch_prolong_trunc_m<double>(hipStream_t, int, int, int, const double*, double*);
 template void launch_restrict_dense_m<double>(hipStream_t, int, int, int, const int*, const int*,
-                                              const double*, const double*, double*);
-template void launch_prolong_dense_m<double>(hipStream_t, int, int, int, const int*,
+                                              const int*, const double*, const double*, double*);
+template void launch_prolong_dense_m<double>(hipStream_t, int, int, int, const int*, const int*,
                                              const double*, const double*, double*);
 
 }  // namespace xdg

@@ -133,90 +133,102 @@ __global__ __launch_bounds__(64) void k_galerkin_dense(int n_cblk, int npf, int 
     }
 }
 
-// Large coarse blocks (npc * npc > 32, aggregation levels that keep the fine
-// degree): one 256-thread workgroup per coarse block.  The contributions of
-// one fine row i (consecutive in the list) are summed first,
-// U = sum_l A_il R_l (A_il and R_l staged in LDS kch at a time), then
-// C += R_i^T U: 2 npf^2 npc flops per contribution plus 2 npf npc^2 per fine
-// row, and one round of global loads per kch contributions.  Contributions
-// and rows are added in list order.
-__global__ __launch_bounds__(256) void k_galerkin_dense_lds(int n_cblk, int npf, int npc, int kch,
-                                                           const int* __restrict__ cptr,
-                                                           const int* __restrict__ cfb,
-                                                           const int* __restrict__ crow,
-                                                           const int* __restrict__ ccol,
-                                                           const double* __restrict__ A,
-                                                           const double* __restrict__ R,
-                                                           double* __restrict__ Ac,
-                                                           const int* __restrict__ list) {
+// Wide Galerkin product in two passes (one wave per item, wave-private LDS,
+// no workgroup barriers), for aggregation levels that keep the fine degree.
+// The contributions of a coarse block (I, L) that share a fine row i form a
+// group g;  pass 1:  U_g = sum over the group's fine blocks (i, l), in list
+// order, of A_il R_l;  pass 2:  C_IL = sum over the groups of (I, L), in order,
+// of R_i^T U_g.  Either pass streams each operand once per use.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kWideQ = 20;     // outputs per lane: 64 * 20 >= 35 * 35
+
+__global__ __launch_bounds__(256) void k_galerkin_u(int n_grp, int npf, int npc,
+                                                    const int* __restrict__ gstart,
+                                                    const int* __restrict__ cfb,
+                                                    const int* __restrict__ ccol,
+                                                    const double* __restrict__ A,
+                                                    const double* __restrict__ R,
+                                                    double* __restrict__ U) {
     extern __shared__ double lds[];
-    if ((int)blockIdx.x >= n_cblk) return;
-    const int cb = list ? list[blockIdx.x] : (int)blockIdx.x;
-    const int nf2 = npf * npf, nfc = npf * npc, nc2 = npc * npc;
-    double* sRi = lds;              // row-major npf x npc
-    double* sU = sRi + nfc;         // row-major npf x npc
-    double* sA = sU + nfc;          // kch column-major npf x npf blocks
-    double* sRl = sA + kch * nf2;   // kch row-major npf x npc blocks
-    constexpr int kQ = 5;           // outputs t = threadIdx.x + 256 q (npc, npf <= 35)
-    double cacc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const int k0 = cptr[cb], k1 = cptr[cb + 1];
-    int k = k0;
-    while (k < k1) {
-        const int i = crow[k];
-        int kend = k + 1;
-        while (kend < k1 && crow[kend] == i) ++kend;
-        double uacc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int e = threadIdx.x; e < nfc; e += blockDim.x) sRi[e] = R[(int64_t)i * nfc + e];
-        for (int c0 = k; c0 < kend; c0 += kch) {
-            const int nk = min(kch, kend - c0);
-            for (int e = threadIdx.x; e < nk * nf2; e += blockDim.x) {
-                const int kk = e / nf2;
-                sA[e] = A[(int64_t)cfb[c0 + kk] * nf2 + (e - kk * nf2)];
-            }
-            for (int e = threadIdx.x; e < nk * nfc; e += blockDim.x) {
-                const int kk = e / nfc;
-                sRl[e] = R[(int64_t)ccol[c0 + kk] * nfc + (e - kk * nfc)];
-            }
-            __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nf2 = npf * npf, nfc = npf * npc;
+    double* sA = lds + (size_t)w * (nf2 + nfc);     // column-major npf x npf
+    double* sR = sA + nf2;                           // row-major npf x npc
+    const int g = (int)blockIdx.x * (int)(blockDim.x >> 6) + w;
+    if (g >= n_grp) return;
+    double u[kWideQ];
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {                  // U[a][m2]
-                const int t = threadIdx.x + 256 * q;
-                if (t < nfc) {
-                    const int a = t / npc, m2 = t - a * npc;
-                    double u = 0.0;
-                    for (int kk = 0; kk < nk; ++kk) {
-                        const double* Ak = sA + kk * nf2;
-                        const double* Rk = sRl + kk * nfc;
-                        for (int bb = 0; bb < npf; ++bb) u += Ak[bb * npf + a] * Rk[bb * npc + m2];
-                    }
-                    uacc[q] += u;
-                }
+    for (int q = 0; q < kWideQ; ++q) u[q] = 0.0;
+    for (int k = gstart[g]; k < gstart[g + 1]; ++k) {
+        const double* Ab = A + (int64_t)cfb[k] * nf2;
+        const double* Rl = R + (int64_t)ccol[k] * nfc;
+        for (int e = lane; e < nf2; e += 64) sA[e] = Ab[e];
+        for (int e = lane; e < nfc; e += 64) sR[e] = Rl[e];
+        wave_sync_lds();
+#pragma unroll
+        for (int q = 0; q < kWideQ; ++q) {
+            const int t = lane + 64 * q;
+            if (t < nfc) {
+                const int a = t / npc, m2 = t - a * npc;
+                double v = 0.0;
+                for (int b = 0; b < npf; ++b) v += sA[b * npf + a] * sR[b * npc + m2];
+                u[q] += v;
             }
-            __syncthreads();
         }
+        wave_sync_lds();
+    }
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const int t = threadIdx.x + 256 * q;
-            if (t < nfc) sU[t] = uacc[q];
+    for (int q = 0; q < kWideQ; ++q) {
+        const int t = lane + 64 * q;
+        if (t < nfc) U[(int64_t)g * nfc + t] = u[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_galerkin_c(int n_cblk, int npf, int npc,
+                                                    const int* __restrict__ cbg,
+                                                    const int* __restrict__ grow,
+                                                    const double* __restrict__ R,
+                                                    const double* __restrict__ U,
+                                                    double* __restrict__ Ac) {
+    extern __shared__ double lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nfc = npf * npc, nc2 = npc * npc;
+    double* sRi = lds + (size_t)w * 2 * nfc;
+    double* sU = sRi + nfc;
+    const int cb = (int)blockIdx.x * (int)(blockDim.x >> 6) + w;
+    if (cb >= n_cblk) return;
+    double c[kWideQ];
+#pragma unroll
+    for (int q = 0; q < kWideQ; ++q) c[q] = 0.0;
+    for (int g = cbg[cb]; g < cbg[cb + 1]; ++g) {
+        const double* Ri = R + (int64_t)grow[g] * nfc;
+        const double* Ug = U + (int64_t)g * nfc;
+        for (int e = lane; e < nfc; e += 64) {
+            sRi[e] = Ri[e];
+            sU[e] = Ug[e];
         }
-        __syncthreads();
+        wave_sync_lds();
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {                      // C[m][m2], column-major
-            const int t = threadIdx.x + 256 * q;
+        for (int q = 0; q < kWideQ; ++q) {
+            const int t = lane + 64 * q;
             if (t < nc2) {
                 const int m2 = t / npc, m = t - m2 * npc;
                 double v = 0.0;
                 for (int a = 0; a < npf; ++a) v += sRi[a * npc + m] * sU[a * npc + m2];
-                cacc[q] += v;
+                c[q] += v;
             }
         }
-        __syncthreads();
-        k = kend;
+        wave_sync_lds();
     }
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        const int t = threadIdx.x + 256 * q;
-        if (t < nc2) Ac[(int64_t)cb * nc2 + t] = cacc[q];
+    for (int q = 0; q < kWideQ; ++q) {
+        const int t = lane + 64 * q;
+        if (t < nc2) Ac[(int64_t)cb * nc2 + t] = c[q];
     }
 }
 
@@ -538,19 +550,24 @@ void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const
 void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
                            const int* cfb, const int* crow, const int* ccol, const double* A,
                            const double* R, double* Ac, const int* list) {
-    if (n_cblk <= 0) return;
-    if (npc * npc > 32) {
-        // contributions staged per round: as many as 48 KB of LDS allows, at most 4
-        const size_t nfc = (size_t)npf * npc, per = (size_t)npf * npf + nfc;
-        const size_t budget = 48 * 1024 / sizeof(double);
-        const int kch = (int)std::max<size_t>(1, std::min<size_t>(4, (budget - 2 * nfc) / per));
-        const size_t lds = (2 * nfc + (size_t)kch * per) * sizeof(double);
-        k_galerkin_dense_lds<<<n_cblk, 256, lds, s>>>(n_cblk, npf, npc, kch, cptr, cfb, crow,
-                                                      ccol, A, R, Ac, list);
-    } else {
+    if (n_cblk > 0)
         k_galerkin_dense<<<n_cblk, 64, 0, s>>>(n_cblk, npf, npc, cptr, cfb, crow, ccol, A, R, Ac,
                                                list);
-    }
+}
+void launch_galerkin_wide(hipStream_t s, int n_grp, int n_cblk, int npf, int npc,
+                          const int* gstart, const int* grow, const int* cbg, const int* cfb,
+                          const int* ccol, const double* A, const double* R, double* U,
+                          double* Ac) {
+    if (n_grp <= 0 || n_cblk <= 0) return;
+    const size_t nf2 = (size_t)npf * npf, nfc = (size_t)npf * npc;
+    // waves per workgroup: as many as 48 KB of LDS allows (at most 4)
+    const size_t budget = 48 * 1024 / sizeof(double);
+    const int w1 = (int)std::max<size_t>(1, std::min<size_t>(4, budget / (nf2 + nfc)));
+    const int w2 = (int)std::max<size_t>(1, std::min<size_t>(4, budget / (2 * nfc)));
+    k_galerkin_u<<<(n_grp + w1 - 1) / w1, 64 * w1, (size_t)w1 * (nf2 + nfc) * sizeof(double),
+                   s>>>(n_grp, npf, npc, gstart, cfb, ccol, A, R, U);
+    k_galerkin_c<<<(n_cblk + w2 - 1) / w2, 64 * w2, (size_t)w2 * 2 * nfc * sizeof(double),
+                   s>>>(n_cblk, npf, npc, cbg, grow, R, U, Ac);
 }
 void launch_transpose_list(hipStream_t s, int n, const int* list, int np, const double* in,
                            double* out) {

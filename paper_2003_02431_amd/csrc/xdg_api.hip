@@ -5,6 +5,7 @@
 #include <numeric>
 
 #include <mutex>
+#include <unordered_map>
 
 #include "xdg_handle.h"
 
@@ -128,6 +129,12 @@ static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* p
         crow[k] = it[k].i;
         ccol[k] = it[k].l;
     }
+    // the products index the table of distinct transfer blocks
+    std::vector<int> rrow(it.size()), rcol(it.size());
+    for (size_t k = 0; k < it.size(); ++k) {
+        rrow[k] = f.h_ridx[crow[k]];
+        rcol[k] = f.h_ridx[ccol[k]];
+    }
     cptr.push_back((int)it.size());
     for (int i = 0; i < ncr; ++i) c.h_rp[i + 1] += c.h_rp[i];
     c.nnzb = (int)c.h_ci.size();
@@ -136,9 +143,28 @@ static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* p
     CHK(h->upload(&c.ci, c.h_ci.data(), c.h_ci.size()));
     CHK(h->upload(&f.g_ptr, cptr.data(), cptr.size()));
     CHK(h->upload(&f.g_fb, cfb.data(), cfb.size()));
-    CHK(h->upload(&f.g_row, crow.data(), crow.size()));
-    CHK(h->upload(&f.g_col, ccol.data(), ccol.size()));
+    CHK(h->upload(&f.g_row, rrow.data(), rrow.size()));
+    CHK(h->upload(&f.g_col, rcol.data(), rcol.size()));
     CHK(h->alloc(&c.A64, (size_t)c.nnzb * c.np * c.np));
+    if (c.np * c.np > 32) {
+        // fine-row groups inside every coarse block's contribution list
+        std::vector<int> gstart, grow, cbg(c.nnzb + 1, 0);
+        for (int cb = 0; cb < c.nnzb; ++cb) {
+            cbg[cb] = (int)gstart.size();
+            for (int k = cptr[cb]; k < cptr[cb + 1]; ++k)
+                if (k == cptr[cb] || crow[k] != crow[k - 1]) {
+                    gstart.push_back(k);
+                    grow.push_back(rrow[k]);
+                }
+        }
+        cbg[c.nnzb] = (int)gstart.size();
+        f.n_grp = (int)gstart.size();
+        gstart.push_back((int)it.size());
+        CHK(h->upload(&f.g_gstart, gstart.data(), gstart.size()));
+        CHK(h->upload(&f.g_grow, grow.data(), grow.size()));
+        CHK(h->upload(&f.g_cbg, cbg.data(), cbg.size()));
+        CHK(h->alloc(&f.g_U, (size_t)f.n_grp * f.np * c.np));
+    }
     return XDG_OK;
 }
 
@@ -176,6 +202,9 @@ static int numeric_setup(xdg_handle* h, const double* raw) {
         Level& c = h->L[t + 1];
         if (f.t_kind == XDG_T_PTRUNC)
             launch_extract_leading(s, f.nnzb, f.np, c.np, f.A64, c.A64);
+        else if (f.g_U)
+            launch_galerkin_wide(s, f.n_grp, c.nnzb, f.np, c.np, f.g_gstart, f.g_grow, f.g_cbg,
+                                 f.g_fb, f.g_col, f.A64, f.R64, f.g_U, c.A64);
         else
             launch_galerkin_dense(s, c.nnzb, f.np, c.np, f.g_ptr, f.g_fb, f.g_row, f.g_col,
                                   f.A64, f.R64, c.A64, nullptr);
@@ -278,14 +307,14 @@ static void vcycle(xdg_handle* h, int l) {
     } else {
         launch_spmv<T>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f), P<T>::x(f),
                        P<T>::b(f), P<T>::r(f), 0, f.next_dir());
-        launch_restrict_dense<T>(h->s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi,
+        launch_restrict_dense<T>(h->s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi, f.ridx,
                                  P<T>::R(f), P<T>::r(f), P<T>::b(c), P<T>::y(f));
     }
     vcycle<T>(h, l + 1);
     if (f.t_kind == XDG_T_PTRUNC)
         launch_prolong_trunc<T>(h->s, f.n_rows, f.np, c.np, P<T>::x(c), P<T>::x(f));
     else
-        launch_prolong_dense<T>(h->s, f.n_rows, f.np, c.np, f.parent, P<T>::R(f), P<T>::x(c),
+        launch_prolong_dense<T>(h->s, f.n_rows, f.np, c.np, f.parent, f.ridx, P<T>::R(f), P<T>::x(c),
                                 P<T>::x(f));
     smooth_more<T>(h, f, h->opt.nu_post);
 }
@@ -532,7 +561,35 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
             CHK(h->alloc(&c.A64, (size_t)c.nnzb * c.np * c.np));
         } else {
             CHK(h->upload(&f.parent, tr.parent, f.n_rows));
-            CHK(h->upload(&f.R64, tr.R, (size_t)f.n_rows * f.np * c.np));
+            {
+                // store every distinct R_i once (equal bit for bit)
+                const size_t bs = (size_t)f.np * c.np;
+                std::unordered_map<uint64_t, std::vector<int>> seen;
+                std::vector<double> table;
+                f.h_ridx.assign(f.n_rows, -1);
+                for (int i = 0; i < f.n_rows; ++i) {
+                    const double* Ri = tr.R + (size_t)i * bs;
+                    uint64_t hsh = 1469598103934665603ull;       // FNV-1a over the bytes
+                    const unsigned char* by = reinterpret_cast<const unsigned char*>(Ri);
+                    for (size_t q = 0; q < bs * sizeof(double); ++q)
+                        hsh = (hsh ^ by[q]) * 1099511628211ull;
+                    int id = -1;
+                    for (int cand : seen[hsh])
+                        if (std::memcmp(table.data() + (size_t)cand * bs, Ri,
+                                        bs * sizeof(double)) == 0) {
+                            id = cand;
+                            break;
+                        }
+                    if (id < 0) {
+                        id = f.n_rblocks++;
+                        seen[hsh].push_back(id);
+                        table.insert(table.end(), Ri, Ri + bs);
+                    }
+                    f.h_ridx[i] = id;
+                }
+                CHK(h->upload(&f.R64, table.data(), table.size()));
+                CHK(h->upload(&f.ridx, f.h_ridx.data(), f.h_ridx.size()));
+            }
             // children lists (ascending fine index)
             std::vector<int> chp(c.n_rows + 1, 0), chi(f.n_rows);
             for (int i = 0; i < f.n_rows; ++i) chp[tr.parent[i] + 1]++;
@@ -542,8 +599,8 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
             CHK(h->upload(&f.chp, chp.data(), chp.size()));
             CHK(h->upload(&f.chi, chi.data(), chi.size()));
             CHK(galerkin_symbolic(h, f, c, tr.parent));
-            if (h->mixed) {
-                const int64_t nrr = (int64_t)f.n_rows * f.np * c.np;
+            if (h->mixed || h->nrhs == kNrhs) {
+                const int64_t nrr = (int64_t)f.n_rblocks * f.np * c.np;
                 CHK(h->alloc(&f.R32, nrr));
                 launch_convert<double, float>(h->s, nrr, f.R64, f.R32);
             }
@@ -682,13 +739,13 @@ extern "C" int xdg_restrict(xdg_handle* h, int32_t level, const double* rf, doub
         if (f.t_kind == XDG_T_PTRUNC)
             launch_restrict_trunc_m<double>(h->s, f.n_rows, f.np, c.np, rf, rc);
         else
-            launch_restrict_dense_m<double>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.R64, rf,
+            launch_restrict_dense_m<double>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.ridx, f.R64, rf,
                                             rc);
     } else if (f.t_kind == XDG_T_PTRUNC)
         launch_restrict_trunc<double>(h->s, f.n_rows, f.np, c.np, rf, rc);
     else
         launch_restrict_dense<double>(h->s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi,
-                                      f.R64, rf, rc, f.y64);
+                                      f.ridx, f.R64, rf, rc, f.y64);
     HIPCHK(hipGetLastError());
     return XDG_OK;
 }
@@ -702,11 +759,13 @@ extern "C" int xdg_prolong(xdg_handle* h, int32_t level, const double* xc, doubl
         if (f.t_kind == XDG_T_PTRUNC)
             launch_prolong_trunc_m<double>(h->s, f.n_rows, f.np, c.np, xc, xf);
         else
-            launch_prolong_dense_m<double>(h->s, f.n_rows, f.np, c.np, f.parent, f.R64, xc, xf);
+            launch_prolong_dense_m<double>(h->s, f.n_rows, f.np, c.np, f.parent, f.ridx, f.R64, xc,
+                                           xf);
     } else if (f.t_kind == XDG_T_PTRUNC)
         launch_prolong_trunc<double>(h->s, f.n_rows, f.np, c.np, xc, xf);
     else
-        launch_prolong_dense<double>(h->s, f.n_rows, f.np, c.np, f.parent, f.R64, xc, xf);
+        launch_prolong_dense<double>(h->s, f.n_rows, f.np, c.np, f.parent, f.ridx, f.R64, xc,
+                                     xf);
     HIPCHK(hipGetLastError());
     return XDG_OK;
 }
@@ -1159,6 +1218,9 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
             Level& f = h->L[t - 1];
             if (f.t_kind == XDG_T_PTRUNC)
                 launch_extract_list(s, (int)bcnt[t], bl, f.np, lv.np, f.A64, lv.A64);
+            else if (f.g_U)     // wide level: the whole product, as in the full set-up
+                launch_galerkin_wide(s, f.n_grp, lv.nnzb, f.np, lv.np, f.g_gstart, f.g_grow,
+                                     f.g_cbg, f.g_fb, f.g_col, f.A64, f.R64, f.g_U, lv.A64);
             else
                 launch_galerkin_dense(s, (int)bcnt[t], f.np, lv.np, f.g_ptr, f.g_fb, f.g_row,
                                       f.g_col, f.A64, f.R64, lv.A64, bl);

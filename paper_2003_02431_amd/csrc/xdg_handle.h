@@ -46,6 +46,12 @@ struct Level {
     // Galerkin contributions forming the next coarser level (dense transfers)
     int *g_ptr = nullptr, *g_fb = nullptr, *g_row = nullptr, *g_col = nullptr;
     std::vector<int> h_fb2cb;       // fine block -> the coarse block it contributes to
+    // wide Galerkin (coarse blocks of more than 32 entries): fine-row groups of
+    // the contribution lists, their fine row, the groups of every coarse block,
+    // and the per-group products A R
+    int n_grp = 0;
+    int *g_gstart = nullptr, *g_grow = nullptr, *g_cbg = nullptr;
+    double* g_U = nullptr;
     // partial update (built on first use): row of every block, cell of every
     // row, level 0: index of the transposed block (l, i) of block (i, l)
     std::vector<int> h_rob, h_cor, h_btr;
@@ -53,6 +59,11 @@ struct Level {
     // transfer to the next coarser level
     int t_kind = -1, npc = 0, n_c = 0;
     int *parent = nullptr, *chp = nullptr, *chi = nullptr;
+    // distinct transfer blocks R64 / R32 (the children of uncut aggregates
+    // repeat 2^D blocks) and, per fine row, the index of its block
+    int* ridx = nullptr;
+    std::vector<int> h_ridx;
+    int n_rblocks = 0;
     double* R64 = nullptr;
     float* R32 = nullptr;
     // work vectors

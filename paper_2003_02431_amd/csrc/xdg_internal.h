@@ -43,13 +43,15 @@ void launch_prolong_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* 
 // rc = R^T rf over the children lists; coarse blocks of more than
 // kMaxTransferModes modes go through tmp (n_f * npc entries: R_i^T rf_i per
 // fine row, then the children sums)
+// (transfer blocks: fine row i uses R + ridx[i] * npf * npc, a table of the
+// distinct R_i blocks)
 template <typename T>
 void launch_restrict_dense(hipStream_t s, int n_c, int n_f, int npf, int npc,
-                           const int* child_ptr, const int* child_idx, const T* R, const T* rf,
-                           T* rc, T* tmp);
+                           const int* child_ptr, const int* child_idx, const int* ridx,
+                           const T* R, const T* rf, T* rc, T* tmp);
 template <typename T>
 void launch_prolong_dense(hipStream_t s, int n_f, int npf, int npc, const int* parent,
-                          const T* R, const T* xc, T* xf);
+                          const int* ridx, const T* R, const T* xc, T* xf);
 void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
                         double* z);
 bool launch_spmv_dot(hipStream_t s, int n_rows, int np, const int* rp, const int* ci,
@@ -65,6 +67,12 @@ void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const
 void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
                            const int* cfb, const int* ci_row, const int* ci_col,
                            const double* A, const double* R, double* Ac, const int* list);
+// the same product for coarse blocks of more than 32 entries, in two passes
+// over the fine-row groups of every coarse block (U: n_grp * npf * npc)
+void launch_galerkin_wide(hipStream_t s, int n_grp, int n_cblk, int npf, int npc,
+                          const int* gstart, const int* grow, const int* cbg, const int* cfb,
+                          const int* ccol, const double* A, const double* R, double* U,
+                          double* Ac);
 void launch_gather_cells(hipStream_t s, int n_cells, int np, const int* cell_ptr,
                          const int* rp, const int* ci, const double* A, const int64_t* doff,
                          double* D, const int* list);
@@ -150,10 +158,10 @@ template <typename T>
 void launch_prolong_trunc_m(hipStream_t s, int n_rows, int npf, int npc, const T* xc, T* xf);
 template <typename T>
 void launch_restrict_dense_m(hipStream_t s, int n_c, int npf, int npc, const int* cptr,
-                             const int* cidx, const T* R, const T* rf, T* rc);
+                             const int* cidx, const int* ridx, const T* R, const T* rf, T* rc);
 template <typename T>
 void launch_prolong_dense_m(hipStream_t s, int n_f, int npf, int npc, const int* parent,
-                            const T* R, const T* xc, T* xf);
+                            const int* ridx, const T* R, const T* xc, T* xf);
 void launch_coarse_gemm16(hipStream_t s, int n, int ld, const double* Ainv, const double* r,
                           double* z);
 template <typename TV>

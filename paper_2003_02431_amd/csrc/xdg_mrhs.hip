@@ -64,14 +64,15 @@ void vcycle_m(xdg_handle* h, int l) {
     } else {
         launch_spmm<float, float, float>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.Ap32,
                                          f.xm, f.bm, f.rm, 0);
-        launch_restrict_dense_m<float>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.R32, f.rm,
+        launch_restrict_dense_m<float>(h->s, c.n_rows, f.np, c.np, f.chp, f.chi, f.ridx, f.R32, f.rm,
                                        c.bm);
     }
     vcycle_m(h, l + 1);
     if (f.t_kind == XDG_T_PTRUNC)
         launch_prolong_trunc_m<float>(h->s, f.n_rows, f.np, c.np, c.xm, f.xm);
     else
-        launch_prolong_dense_m<float>(h->s, f.n_rows, f.np, c.np, f.parent, f.R32, c.xm, f.xm);
+        launch_prolong_dense_m<float>(h->s, f.n_rows, f.np, c.np, f.parent, f.ridx, f.R32, c.xm,
+                                      f.xm);
     sweeps_m(h, f, false, h->opt.nu_post);
 }
 

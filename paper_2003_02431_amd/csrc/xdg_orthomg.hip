@@ -66,14 +66,14 @@ int om_cycle(xdg_handle* h, int l) {
     if (f.t_kind == XDG_T_PTRUNC)
         launch_restrict_trunc<double>(s, f.n_rows, f.np, c.np, h->omR[l], c.b64);
     else
-        launch_restrict_dense<double>(s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi, f.R64,
-                                      h->omR[l], c.b64, h->omT[l]);
+        launch_restrict_dense<double>(s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi, f.ridx,
+                                      f.R64, h->omR[l], c.b64, h->omT[l]);
     CHK(om_solve_level(h, l + 1, c.b64));
     HIPCHK(hipMemsetAsync(h->omT[l], 0, n * sizeof(double), s));
     if (f.t_kind == XDG_T_PTRUNC)
         launch_prolong_trunc<double>(s, f.n_rows, f.np, c.np, h->omX[l + 1], h->omT[l]);
     else
-        launch_prolong_dense<double>(s, f.n_rows, f.np, c.np, f.parent, f.R64, h->omX[l + 1],
+        launch_prolong_dense<double>(s, f.n_rows, f.np, c.np, f.parent, f.ridx, f.R64, h->omX[l + 1],
                                      h->omT[l]);
     CHK(om_rm(h, l, h->omT[l]));
     // post-smoother on the current residual

@@ -389,7 +389,7 @@ def test_update_matrix_and_errors(torch):
     assert e.value.code == B.XDG_ENOTSPD
 
 
-@pytest.mark.parametrize("name", ["c2n8", "c2n16", "c4n8p4"])
+@pytest.mark.parametrize("name", ["c2n8", "c2n16", "c4n8p4", "c2n8hp"])
 def test_update_cells_equals_full_update(name, torch):
     """New values with the rows and columns of a set of cells scaled (the cut
     cells carrying both species, S M S with S = 1.25 there, still SPD): the
@@ -461,17 +461,23 @@ def test_update_cells_equals_full_update(name, torch):
     Sp.close()
 
 
+# the benchmark's smoother on the 32^3 workload (bench.py defaults)
+BENCH_NU, BENCH_OMEGA = 1, 0.9
+
+
 def test_full_size_sampled(torch):
-    """The 32^3 p=3 workload in the launch configuration the benchmark uses:
-    sampled SpMV rows against the oracle, every Galerkin level in full, and
-    the oracle's residual of the GPU solution."""
+    """The 32^3 p=3 workload in the launch configuration the benchmark uses
+    (its hierarchy and smoother): sampled SpMV rows against the oracle, every
+    Galerkin level in full, sweeps, a V-cycle and the PCG iterate against the
+    oracle, and the oracle's residual of the GPU solution."""
     from oracle import mg
     from paper_2003_02431_amd import binding as B
     from xdg_inputs import problems
     _log("[gpu-parity] generating 32^3 p=3 workload")
     pr = problems.c2(seed=0, n=32, verbose=True)
     A = mg.block_matrix(pr.row_ptr, pr.col_idx, pr.val)
-    S = B.Solver(pr, B.options(rtol=1e-10, maxit=600))
+    S = B.Solver(pr, B.options(rtol=1e-10, maxit=600, nu_pre=BENCH_NU, nu_post=BENCH_NU,
+                               omega=BENCH_OMEGA))
     rng = np.random.default_rng(15)
     x = rng.uniform(-1, 1, A.shape[0])
     y = S.vec(0)
@@ -481,7 +487,7 @@ def test_full_size_sampled(torch):
     ref = A[idx] @ x
     assert _rel(y.cpu().numpy()[idx], ref) <= 1e-13
     _log("[gpu-parity] oracle hierarchy at 32^3")
-    H = mg.hierarchy_of(pr)
+    H = mg.hierarchy_of(pr, omega=BENCH_OMEGA, nu=BENCH_NU)
     for l in range(1, H.nlev):
         rp, ci, val = B.xdg_get_level_matrix(S.h, l)
         G = mg.block_matrix(rp, ci, val)
@@ -511,7 +517,7 @@ def test_full_size_sampled(torch):
     bb, x0 = rng.uniform(-1, 1, (2, A.shape[0]))
     xsw = S.vec(0, x0)
     B.xdg_smooth(S.h, 0, S.vec(0, bb), xsw, 2)
-    esw = _rel(xsw.cpu().numpy(), mg.jacobi(H.A[0], H.Dinv[0], bb, x0, 0.7, 2))
+    esw = _rel(xsw.cpu().numpy(), mg.jacobi(H.A[0], H.Dinv[0], bb, x0, BENCH_OMEGA, 2))
     kc = np.linalg.cond(H.A[-1].toarray())
     ev = _rel(z1.cpu().numpy(), H.vcycle(r1))
     _log(f"  32^3: two sweeps rel err {esw:.2e} (cell kappa {kmax:.1e}), V-cycle rel err "
@@ -523,7 +529,7 @@ def test_full_size_sampled(torch):
     from oracle import mg_omp
     if not os.path.exists(mg_omp.LIB):
         mg_omp.build()
-    O = mg_omp.OmpHierarchy(pr)
+    O = mg_omp.OmpHierarchy(pr, omega=BENCH_OMEGA, nu=BENCH_NU)
     xo, ho, ito = O.pcg(pr.b, rtol=1e-10, maxit=600)
     O.close()
     B.xdg_set_tolerance(S.h, 1e-300, ito)

@@ -137,9 +137,11 @@ def _vcycle_dense(H, level):
     return (I - E) @ np.linalg.inv(A)
 
 
-def test_vcycle_closed_form_and_spd(pr2, pr3, pr3h):
+@pytest.mark.parametrize("nu,omega", [(2, 0.7), (1, 0.9)])
+def test_vcycle_closed_form_and_spd(nu, omega, pr2, pr3, pr3h):
+    """(2, 0.7): the configs' smoother; (1, 0.9): the benchmark's."""
     for pr in (pr2, pr3, pr3h):
-        H = mg.hierarchy_of(pr)
+        H = mg.hierarchy_of(pr, omega=omega, nu=nu)
         L = H.A[0].shape[0]
         B = np.column_stack([H.vcycle(e) for e in np.eye(L)])
         Bd = _vcycle_dense(H, 0)
