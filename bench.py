@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the level-0 SpMV from the FETCH_SIZE / WRITE_SIZE
 # counter passes (scaled by a plain copy of known size), valid only for the
 # kernel source they were taken on.
-SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "43f5b4274efc2df6", "bytes": 771.6e6,
+SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "e4f0ad83b299f8db", "bytes": 771.6e6,
                 "summary": "profiles/k_bsr_spmv_f64_np20_32cubed_hbm_counters.md"}
 
 
@@ -603,8 +603,11 @@ def main():
         log(f"[bench] mixed: {tm} iters {itm} relres {frm:.2e}; "
             f"to rel.res 1e-10: {te} iters {ite}")
 
-    # the paper's orthonormalisation multigrid as the solver (FP64)
-    So = B.Solver(pr, opts(krylov=B.XDG_ORTHOMG, restart=30, rtol=1e-8, maxit=1000))
+    # the paper's orthonormalisation multigrid as the solver (FP64); it stalls
+    # with one sweep at omega 0.9 (rel.res 1.4e-6 after 1000 cycles) and runs
+    # with its own smoother setting, two sweeps at omega 0.7
+    So = B.Solver(pr, B.options(krylov=B.XDG_ORTHOMG, restart=30, rtol=1e-8, maxit=1000,
+                                nu_pre=2, nu_post=2, omega=0.7))
     xo = So.vec(0)
     B.xdg_update_matrix(So.h, val_dev)
     B.xdg_solve(So.h, b_dev, xo, hist_cap=2000)         # warm-up
@@ -621,6 +624,7 @@ def main():
     So.close()
     orthomg = dict(time_s=round(float(np.median(to)), 5), cycles=ito, relres=fro,
                    err_vs_oracle="orthomg_1e-8", restart=30,
+                   smoother="block-Jacobi 2+2 omega=0.7",
                    note="residual minimisation after pre-smoother, coarse correction and "
                         "post-smoother on every level (3 directions per cycle)")
     log(f"[bench] orthomg: {to} cycles {ito} relres {fro:.2e}")
