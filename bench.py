@@ -30,27 +30,49 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the level-0 SpMV from the FETCH_SIZE / WRITE_SIZE
-# counter passes (scaled by a plain copy of known size), valid only for the
-# kernel source they were taken on.
-SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "e4f0ad83b299f8db", "bytes": 771.6e6,
+# Bytes per launch of the level-0 SpMV below L2 from the FETCH_SIZE /
+# WRITE_SIZE counter passes (scaled by a plain copy of known size; reads
+# served by the Infinity cache included), valid only for the kernel source
+# they were taken on.
+SPMV_TRAFFIC = {"kernel_source_sha256_prefix": "e968977e05fea3ab",
+                "bytes": {"general": 773.6e6, "symmetric": 653.9e6},
                 "summary": "profiles/k_bsr_spmv_f64_np20_32cubed_hbm_counters.md"}
 
 
-def spmv_traffic():
+def spmv_traffic(sym):
     import hashlib
     src = os.path.join(ROOT, "paper_2003_02431_amd", "csrc", "k_level.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return SPMV_TRAFFIC["bytes"] if sha == SPMV_TRAFFIC["kernel_source_sha256_prefix"] else None
+    if sha != SPMV_TRAFFIC["kernel_source_sha256_prefix"]:
+        return None
+    return SPMV_TRAFFIC["bytes"]["symmetric" if sym else "general"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(pr, word=8):
+def spmv_bytes(pr, word=8, sym=False):
+    """Algorithmic bytes of one level-0 block SpMV.  General storage: every
+    block, its column index, the row pointers, x once and y.  Symmetric
+    storage (diagonal and upper blocks, lower blocks read as transposes of the
+    stored ones): every stored block once, the upper and lower lists, x once
+    and y; the second read of a stored block is not counted."""
     nnzb, npm, rows = pr.col_idx.size, pr.np, pr.n_rows
-    return nnzb * npm * npm * word + 4 * nnzb + 4 * (rows + 1) + 2 * rows * npm * word
+    vec = 2 * rows * npm * word
+    if not sym:
+        return nnzb * npm * npm * word + 4 * nnzb + 4 * (rows + 1) + vec
+    rp = np.asarray(pr.row_ptr)
+    row_of = np.repeat(np.arange(rows), np.diff(rp))
+    nu = int(np.count_nonzero(np.asarray(pr.col_idx) >= row_of))
+    nl = nnzb - nu
+    return nu * npm * npm * word + 4 * nu + 8 * (rows + 1) + 8 * nl + vec
+
+
+def uses_symmetric(pr):
+    """The library keeps level 0 in symmetric storage for 20-mode blocks
+    (single column, option symmetric = 1, the default of the binding)."""
+    return int(pr.np) == 20
 
 
 def time_spmv(torch, B, S, level, reps=50):
@@ -469,11 +491,17 @@ def main():
         y = S.vec(0)
         for _ in range(20):
             B.xdg_spmv(S.h, 0, x, y)
+        Sg = B.Solver(pr, opts(krylov=B.XDG_CG, rtol=1e-8, maxit=1000, symmetric=0))
+        for _ in range(20):
+            B.xdg_spmv(Sg.h, 0, x, y)
         big = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         out = torch.empty_like(big)
         out.copy_(big)
         torch.cuda.synchronize()
-        log(f"[bench] profile-spmv: 20 launches, bytes/launch {spmv_bytes(pr)}; copy 1 GiB")
+        log(f"[bench] profile-spmv: 20 launches on symmetric storage (bytes/launch "
+            f"{spmv_bytes(pr, sym=True)}), 20 on general storage ({spmv_bytes(pr)}); "
+            f"copy 1 GiB")
+        Sg.close()
         return
 
     if args.profile_solve:
@@ -659,10 +687,43 @@ def main():
     log(f"[bench] partial update: {partial_update}")
 
     # roofline of the level-0 block SpMV
+    sym = uses_symmetric(pr)
     t_spmv = time_spmv(torch, B, S, 0)
-    nbytes = spmv_bytes(pr)
+    nbytes = spmv_bytes(pr, sym=sym)
+    full_bytes = spmv_bytes(pr)
     achieved = nbytes / t_spmv / 1e9
-    log(f"[bench] spmv: {t_spmv * 1e6:.1f} us/launch, {achieved:.0f} GB/s")
+    log(f"[bench] spmv: {t_spmv * 1e6:.1f} us/launch, {achieved:.0f} GB/s "
+        f"({full_bytes / t_spmv / 1e9:.0f} GB/s of full-matrix bytes)")
+
+    # the same step on general storage (every block read, as for a
+    # non-symmetric matrix)
+    general = None
+    if sym:
+        Sg = B.Solver(pr, opts(krylov=B.XDG_CG, rtol=1e-8, maxit=1000, symmetric=0))
+        xg = Sg.vec(0)
+        tg, itg = [], []
+        for k in range(4):
+            xg.zero_()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            B.xdg_update_matrix(Sg.h, val_dev)
+            rcg, itk, frg, _ = B.xdg_solve(Sg.h, b_dev, xg, hist_cap=2000)
+            torch.cuda.synchronize()
+            if k:
+                tg.append(time.perf_counter() - t2)
+                itg.append(itk)
+        tg_spmv = time_spmv(torch, B, Sg, 0)
+        keep["general_storage_1e-8"] = xg.clone()
+        gb = full_bytes / tg_spmv / 1e9
+        general = dict(ms_per_step=round(float(np.median(tg)) * 1e3, 3),
+                       iters=int(np.median(itg)), relres=frg,
+                       err_vs_oracle="general_storage_1e-8",
+                       spmv_us=round(tg_spmv * 1e6, 2), spmv_gbs=round(gb, 1),
+                       spmv_frac=round(gb / HBM_PEAK_GBS, 4),
+                       note="symmetric = 0: every block of the level-0 matrix read by the "
+                            "solve kernels (the form for non-symmetric matrices)")
+        Sg.close()
+        log(f"[bench] general storage: {general}")
 
     cpu, errs = None, {}
     if not args.no_cpu_baseline:
@@ -675,7 +736,8 @@ def main():
         errs["oracle_x*"] = f"oracle PCG to rel.res 1e-13 ({it_star} iterations in all)"
         log(f"[bench] errors against the oracle's x*: {errs}")
     err8 = errs.get("fp64_cg_1e-8")
-    for d in (mixed, mixed and mixed["at_err_1e_8"], mixed and mixed["flexible_cg"], orthomg):
+    for d in (mixed, mixed and mixed["at_err_1e_8"], mixed and mixed["flexible_cg"], orthomg,
+              general):
         if d:
             d["err_vs_oracle"] = errs.get(d["err_vs_oracle"])
 
@@ -709,11 +771,21 @@ def main():
         "mixed_precision": mixed,
         "orthomg": orthomg,
         "partial_update": partial_update,
+        "general_storage": general,
         "spmv_gbs": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": spmv_traffic(), "kernel": "k_bsr_spmv<double,20> level 0",
-                     "bytes_per_launch": int(nbytes), "us_per_launch": round(t_spmv * 1e6, 2)},
+                     "traffic": spmv_traffic(sym),
+                     "kernel": ("k_bsr_spmv_sym<double,20>" if sym else "k_bsr_spmv<double,20>")
+                               + " level 0",
+                     "bytes_per_launch": int(nbytes), "us_per_launch": round(t_spmv * 1e6, 2),
+                     "full_matrix_bytes_per_launch": int(full_bytes),
+                     "full_matrix_gbs": round(full_bytes / t_spmv / 1e9, 1),
+                     "note": ("symmetric storage: bytes_per_launch counts every stored "
+                              "(diagonal or upper) block once; the transposed second read of "
+                              "an off-diagonal block is served mostly by the Infinity cache, "
+                              "so full_matrix_gbs (every block of the matrix per launch) can "
+                              "exceed the HBM peak") if sym else None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -95,6 +95,16 @@ typedef struct {
                               /* matvec and restart residuals on FP64 MFMA      */
     double  rtol;             /* stop at ||b - M x||_2 / ||b||_2 <= rtol        */
     double  omega;            /* Jacobi damping                                 */
+    int32_t symmetric;        /* 1: the level-0 matrix is symmetric (the SIP    */
+                              /* form of Eq. DefSIP is): single-column solves   */
+                              /* read its diagonal and upper blocks only and    */
+                              /* take each lower block (i, j) as the transpose  */
+                              /* of the stored (j, i); used for np = 20, other  */
+                              /* block sizes read every block.  The pattern     */
+                              /* must then be symmetric (else XDG_EINVAL); the  */
+                              /* values of the lower blocks are not read by the */
+                              /* solve (set-up and xdg_get_level_matrix use     */
+                              /* all blocks).  0: every block is read.          */
 } xdg_options;
 
 /* Copies the level-0 system and transfers to the device, forms every coarse

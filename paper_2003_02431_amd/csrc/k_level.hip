@@ -349,6 +349,221 @@ __global__ __launch_bounds__(256) void k_jacobi(int n_cells, int np_rt, const in
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric level matrix kept as its diagonal and upper blocks (column >= row,
+// the SIP matrix being symmetric).  Row i's product is its upper stream
+// (contiguous, as above) plus, for every lower block (i, j), the transpose of
+// the stored block (j, i):  (M_ji^T x_j)_r = sum_c M_ji(c, r) x_j(c),  i.e. the
+// stored column r dotted with x_j.  The stored block was streamed when row j
+// was, a few thousand rows earlier, so the second read mostly hits the
+// memory-side cache; HBM sees each off-diagonal block once.
+//
+// Lower-block lane map: lane = cl * L + q holds rows q*V .. q*V+V-1 of stored
+// columns cl, cl + CT, ... (CT columns per load step, KT = Np / CT steps per
+// block), i.e. one partial sum per output mode r = m*CT + cl; the L lanes of a
+// column are then added in lane order.
+template <typename T, int NP>
+struct SymCfg {
+    using R = RowCfg<T, NP, true>;
+    static constexpr int L = R::L;
+    static constexpr int ct_of(int c) { return (NP % c == 0 && c * L <= 64) ? c : ct_of(c - 1); }
+    static constexpr int CT = ct_of(NP);
+    static constexpr int KT = NP / CT;
+};
+
+template <typename T, int NP>
+__device__ __forceinline__ void lower_stream(int l0, int nl, const int* __restrict__ lci,
+                                             const int* __restrict__ lidx,
+                                             const T* __restrict__ As, const T* __restrict__ x,
+                                             int lane, T (&acc)[SymCfg<T, NP>::KT]) {
+    using S = SymCfg<T, NP>;
+    constexpr int V = S::R::VEC;
+    const int q = lane % S::L;
+    const int cl = lane / S::L;
+    const bool act = cl < S::CT;
+    const int creg = lane < nl ? lci[l0 + lane] : 0;
+    const int treg = lane < nl ? lidx[l0 + lane] : 0;
+    for (int k = 0; k < nl; ++k) {
+        int j = __shfl(creg, k & 63, 64);
+        int t = __shfl(treg, k & 63, 64);
+        if (k >= 64) {
+            j = lci[l0 + k];
+            t = lidx[l0 + k];
+        }
+        if (act) {
+            T xv[V];
+            load_vec<T, V>(x + (int64_t)j * NP + q * V, xv);
+            const T* Sb = As + (int64_t)t * (NP * NP) + q * V;
+#pragma unroll
+            for (int m = 0; m < S::KT; ++m) {
+                T a[V];
+                load_vec<T, V>(Sb + (m * S::CT + cl) * NP, a);
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[m] += a[v] * xv[v];
+            }
+        }
+    }
+    // lanes with q == 0 receive the sum over the column's L lanes (lane order)
+#pragma unroll
+    for (int m = 0; m < S::KT; ++m) {
+        T tot = acc[m];
+        for (int d = 1; d < S::L; ++d) tot += __shfl(acc[m], min(lane + d, 63), 64);
+        acc[m] = tot;
+    }
+}
+
+// SpMV modes of k_bsr_spmv on the symmetric storage: two waves per block row,
+// the first streams the upper blocks, the second the lower (transposed) ones;
+// the sums meet in LDS (upper + lower, fixed order).
+template <typename T, int NP, int MODE>
+__global__ __launch_bounds__(256) void k_bsr_spmv_sym(int n_rows, const int* __restrict__ urp,
+                                                      const int* __restrict__ uci,
+                                                      const T* __restrict__ As,
+                                                      const int* __restrict__ lrp,
+                                                      const int* __restrict__ lci,
+                                                      const int* __restrict__ lidx,
+                                                      const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ y,
+                                                      int npc, double* __restrict__ dpart,
+                                                      int rev) {
+    using R = RowCfg<T, NP, true>;
+    using S = SymCfg<T, NP>;
+    __shared__ T part[2][NP];
+    __shared__ double rowdot[2];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int row0 = uniform(blockIdx.x * 2 + (w >> 1));
+    const int half = w & 1;
+    const bool valid = row0 < n_rows;
+    const int row = rev ? n_rows - 1 - row0 : row0;
+    T acc[R::VEC];
+#pragma unroll
+    for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
+    if (!half) {
+        if (valid) {
+            const int b0 = uniform(urp[row]);
+            row_stream<T, NP, true>(b0, uniform(urp[row + 1]) - b0, uci, As, x, lane, acc);
+        }
+        reduce_groups<T, R::VEC>(acc, R::L, R::C);
+    } else {
+        T lacc[S::KT];
+#pragma unroll
+        for (int m = 0; m < S::KT; ++m) lacc[m] = 0;
+        int l0 = 0, nl = 0;
+        if (valid) {
+            l0 = uniform(lrp[row]);
+            nl = uniform(lrp[row + 1]) - l0;
+        }
+        lower_stream<T, NP>(l0, nl, lci, lidx, As, x, lane, lacc);
+        const int q = lane % S::L, cl = lane / S::L;
+        if (q == 0 && cl < S::CT) {
+#pragma unroll
+            for (int m = 0; m < S::KT; ++m) part[w >> 1][m * S::CT + cl] = lacc[m];
+        }
+    }
+    __syncthreads();
+    double dot = 0.0;
+    if (!half && valid && lane < R::L) {
+#pragma unroll
+        for (int v = 0; v < R::VEC; ++v) {
+            const int r = lane * R::VEC + v;
+            const T sum = acc[v] + part[w >> 1][r];
+            const int64_t o = (int64_t)row * NP + r;
+            if (MODE == SPMV_AX || MODE == SPMV_AX_DOT) y[o] = sum;
+            else if (MODE == SPMV_RESID) y[o] = b[o] - sum;
+            else if (r < npc) y[(int64_t)row * npc + r] = b[o] - sum;
+            if (MODE == SPMV_AX_DOT) dot += (double)x[o] * (double)sum;
+        }
+    }
+    if constexpr (MODE == SPMV_AX_DOT) {
+        for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+        if (!half && lane == 0) rowdot[w >> 1] = dot;
+        __syncthreads();
+        if (threadIdx.x == 0) dpart[blockIdx.x] = rowdot[0] + rowdot[1];
+    }
+}
+
+// Damped block-Jacobi sweep (x_in given) on the symmetric storage: one wave
+// per cell as in k_jacobi, each row's residual formed from its upper and
+// lower streams.
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void k_jacobi_sym(int n_cells, const int* __restrict__ cell_ptr,
+                                                    const int* __restrict__ urp,
+                                                    const int* __restrict__ uci,
+                                                    const T* __restrict__ As,
+                                                    const int* __restrict__ lrp,
+                                                    const int* __restrict__ lci,
+                                                    const int* __restrict__ lidx,
+                                                    const int64_t* __restrict__ doff,
+                                                    const T* __restrict__ D,
+                                                    const T* __restrict__ b,
+                                                    const T* __restrict__ xin,
+                                                    T* __restrict__ xout, T omega, int rev) {
+    using R = RowCfg<T, NP, true>;
+    using S = SymCfg<T, NP>;
+    constexpr int V = R::VEC;
+    __shared__ T res[4][kMaxCell];
+    __shared__ T lo[4][NP];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int cell0 = uniform(blockIdx.x * 4 + w);
+    if (cell0 >= n_cells) return;
+    const int cell = rev ? n_cells - 1 - cell0 : cell0;
+    const int r0 = uniform(cell_ptr[cell]), r1 = uniform(cell_ptr[cell + 1]);
+    const int nc = (r1 - r0) * NP;
+    const int q = lane % S::L, cl = lane / S::L;
+    for (int row = r0; row < r1; ++row) {
+        const int64_t ob = (int64_t)row * NP;
+        T acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0;
+        const int b0 = uniform(urp[row]);
+        row_stream<T, NP, true>(b0, uniform(urp[row + 1]) - b0, uci, As, xin, lane, acc);
+        reduce_groups<T, V>(acc, R::L, R::C);
+        T lacc[S::KT];
+#pragma unroll
+        for (int m = 0; m < S::KT; ++m) lacc[m] = 0;
+        const int l0 = uniform(lrp[row]);
+        lower_stream<T, NP>(l0, uniform(lrp[row + 1]) - l0, lci, lidx, As, xin, lane, lacc);
+        if (q == 0 && cl < S::CT) {
+#pragma unroll
+            for (int m = 0; m < S::KT; ++m) lo[w][m * S::CT + cl] = lacc[m];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < R::L) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int r = lane * V + v;
+                res[w][(row - r0) * NP + r] = b[ob + r] - (acc[v] + lo[w][r]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const T* Dc = D + doff[cell];
+    const int64_t base = (int64_t)r0 * NP;
+    if (nc <= 64 * V) {
+        T acc[V];
+        dense_apply<T, V>(Dc, nc, res[w], lane, acc);
+        if (lane < nc / V) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int64_t o = base + lane * V + v;
+                xout[o] = xin[o] + omega * acc[v];
+            }
+        }
+    } else {
+        for (int o = lane; o < nc; o += 64) {
+            T acc = 0;
+            for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * res[w][c];
+            xout[base + o] = xin[base + o] + omega * acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Small blocks (Np <= 8, the p1 and aggregation levels): a block row holds
 // only ~7 Np^2 entries, so with one wave per row the kernels are bound by
 // per-wave overhead.  Here a group of kGS = 16 lanes takes one block row
@@ -765,6 +980,39 @@ void launch_jacobi(hipStream_t s, bool first, int n_cells, int np, const int* cp
     else jacobi_np<T, false>(s, n_cells, np, cp, rp, ci, A, doff, D, b, xin, xout, omega, r);
 }
 
+template <typename T, int MODE>
+static void spmv_sym_mode(hipStream_t s, int n_rows, const SymRows<T>& m, const T* x,
+                          const T* b, T* y, int npc, double* dpart, int rev) {
+    k_bsr_spmv_sym<T, kSymNp, MODE><<<nblk(n_rows, 2), 256, 0, s>>>(
+        n_rows, m.urp, m.uci, m.A, m.lrp, m.lci, m.lidx, x, b, y, npc, dpart, rev);
+}
+
+template <typename T>
+void launch_spmv_sym(hipStream_t s, int mode, int n_rows, const SymRows<T>& m, const T* x,
+                     const T* b, T* y, int npc, bool rev) {
+    const int r = rev ? 1 : 0;
+    if (mode == SPMV_AX) spmv_sym_mode<T, SPMV_AX>(s, n_rows, m, x, b, y, npc, nullptr, r);
+    else if (mode == SPMV_RESID)
+        spmv_sym_mode<T, SPMV_RESID>(s, n_rows, m, x, b, y, npc, nullptr, r);
+    else spmv_sym_mode<T, SPMV_RESID_TRUNC>(s, n_rows, m, x, b, y, npc, nullptr, r);
+}
+
+void launch_spmv_dot_sym(hipStream_t s, int n_rows, const SymRows<double>& m, const double* x,
+                         double* y, double* partial, double* out, bool rev) {
+    const unsigned nb = nblk(n_rows, 2);
+    spmv_sym_mode<double, SPMV_AX_DOT>(s, n_rows, m, x, nullptr, y, 0, partial, rev ? 1 : 0);
+    launch_dot_final(s, partial, (int)nb, out);
+}
+
+template <typename T>
+void launch_jacobi_sym(hipStream_t s, int n_cells, const int* cp, const SymRows<T>& m,
+                       const int64_t* doff, const T* D, const T* b, const T* xin, T* xout,
+                       T omega, bool rev) {
+    k_jacobi_sym<T, kSymNp><<<nblk(n_cells, 4), 256, 0, s>>>(n_cells, cp, m.urp, m.uci, m.A,
+                                                             m.lrp, m.lci, m.lidx, doff, D, b,
+                                                             xin, xout, omega, rev ? 1 : 0);
+}
+
 template <typename T>
 void launch_restrict_trunc(hipStream_t s, int n_rows, int npf, int npc, const T* rf, T* rc) {
     k_restrict_trunc<T><<<nblk((int64_t)n_rows * npc, 256), 256, 0, s>>>(n_rows, npf, npc, rf, rc);
@@ -813,7 +1061,12 @@ void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const 
                                            const int*, const int*, const T*, const T*, T*,     \
                                            T*);                                                \
     template void launch_prolong_dense<T>(hipStream_t, int, int, int, const int*, const int*,  \
-                                          const T*, const T*, T*);
+                                          const T*, const T*, T*);                     \
+    template void launch_spmv_sym<T>(hipStream_t, int, int, const SymRows<T>&, const T*,       \
+                                     const T*, T*, int, bool);                                 \
+    template void launch_jacobi_sym<T>(hipStream_t, int, const int*, const SymRows<T>&,        \
+                                       const int64_t*, const T*, const T*, const T*, T*, T,    \
+                                       bool);
 XDG_INST(double)
 XDG_INST(float)
 #undef XDG_INST

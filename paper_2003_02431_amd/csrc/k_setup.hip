@@ -78,6 +78,17 @@ __global__ void k_extract_leading(int64_t nnzb, int npf, int npc, const double* 
     Ac[t] = A[b * npf * npf + (int64_t)c * npf + r];
 }
 
+// out[k] = in[idx[k]] block by block (the upper blocks of a symmetric level)
+template <typename Tin, typename Tout>
+__global__ void k_gather_blocks(int64_t n, int bs, const int* __restrict__ idx,
+                                const Tin* __restrict__ in, Tout* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * bs) return;
+    const int64_t k = t / bs;
+    const int e = (int)(t - k * bs);
+    out[t] = (Tout)in[(int64_t)idx[k] * bs + e];
+}
+
 // one workgroup per coarse block; thread (m, m2) of the block computes
 // sum_k sum_a sum_b R_i[a][m] A_fb[a][b] R_l[b][m2]
 __global__ __launch_bounds__(64) void k_galerkin_dense(int n_cblk, int npf, int npc,
@@ -543,6 +554,15 @@ void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* 
     const size_t lds = (size_t)bpg * np * np * sizeof(double);
     k_transpose_blocks<T><<<nblk(nnzb, bpg), 256, lds, s>>>(nnzb, np, bpg, in, out);
 }
+template <typename Tin, typename Tout>
+void launch_gather_blocks(hipStream_t s, int64_t n, int bs, const int* idx, const Tin* in,
+                          Tout* out) {
+    if (n > 0) k_gather_blocks<Tin, Tout><<<nblk(n * bs, 256), 256, 0, s>>>(n, bs, idx, in, out);
+}
+template void launch_gather_blocks<double, double>(hipStream_t, int64_t, int, const int*,
+                                                   const double*, double*);
+template void launch_gather_blocks<double, float>(hipStream_t, int64_t, int, const int*,
+                                                  const double*, float*);
 void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const double* A,
                             double* Ac) {
     k_extract_leading<<<nblk(nnzb * npc * npc, 256), 256, 0, s>>>(nnzb, npf, npc, A, Ac);

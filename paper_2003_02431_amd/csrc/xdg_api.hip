@@ -191,12 +191,30 @@ static int invert_coarsest(xdg_handle* h, Level& lv) {
 // Numeric phase of the set-up from level-0 values `raw` (device, row-major
 // blocks): layout change, Galerkin chain, cell-block and coarsest inverses,
 // FP32 copies.  Errors of the inversions are reported through d_err.
+// the symmetric level's upper blocks from its full FP64 blocks
+static void sym_refresh(xdg_handle* h, Level& lv) {
+    if (lv.sym)
+        launch_gather_blocks<double, double>(h->s, lv.nnzb_u, lv.np * lv.np, lv.ufull, lv.A64,
+                                             lv.As64);
+}
+
+// FP32 copies of a level's operator and cell inverses (mixed precision)
+static void convert_level32(xdg_handle* h, Level& lv) {
+    if (lv.sym)
+        launch_gather_blocks<double, float>(h->s, lv.nnzb_u, lv.np * lv.np, lv.ufull, lv.A64,
+                                            lv.As32);
+    else
+        launch_convert<double, float>(h->s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
+    launch_convert<double, float>(h->s, lv.dsize, lv.D64, lv.D32);
+}
+
 static int numeric_setup(xdg_handle* h, const double* raw) {
     hipStream_t s = h->s;
     const int nl = (int)h->L.size();
     HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), s));
     Level& L0 = h->L[0];
     launch_transpose_blocks<double>(s, L0.nnzb, L0.np, raw, L0.A64);
+    sym_refresh(h, L0);
     for (int t = 0; t + 1 < nl; ++t) {
         Level& f = h->L[t];
         Level& c = h->L[t + 1];
@@ -211,13 +229,8 @@ static int numeric_setup(xdg_handle* h, const double* raw) {
     }
     for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l]));
     CHK(invert_coarsest(h, h->L[nl - 1]));
-    if (h->mixed) {
-        for (int l = 0; l + 1 < nl; ++l) {
-            Level& lv = h->L[l];
-            launch_convert<double, float>(s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
-            launch_convert<double, float>(s, lv.dsize, lv.D64, lv.D32);
-        }
-    }
+    if (h->mixed)
+        for (int l = 0; l + 1 < nl; ++l) convert_level32(h, h->L[l]);
     if (h->nrhs == kNrhs) CHK(mrhs_numeric(h));
     HIPCHK(hipGetLastError());
     return XDG_OK;
@@ -233,6 +246,60 @@ static int check_setup_error(xdg_handle* h) {
 }
 
 // ---------------------------------------------------------------------------
+// Level operators on the level's storage
+
+template <typename T>
+void xdg::level_spmv(xdg_handle* h, Level& lv, int mode, const T* x, const T* b, T* y,
+                     int npc) {
+    const bool rev = lv.next_dir();
+    if (lv.sym)
+        launch_spmv_sym<T>(h->s, mode, lv.n_rows, P<T>::sym(lv), x, b, y, npc, rev);
+    else
+        launch_spmv<T>(h->s, mode, lv.n_rows, lv.np, lv.rp, lv.ci, P<T>::A(lv), x, b, y, npc,
+                       rev);
+}
+template void xdg::level_spmv<double>(xdg_handle*, Level&, int, const double*, const double*,
+                                      double*, int);
+template void xdg::level_spmv<float>(xdg_handle*, Level&, int, const float*, const float*,
+                                     float*, int);
+
+void xdg::level_spmv_dot(xdg_handle* h, Level& lv, const double* x, double* y, double* out) {
+    const bool rev = lv.next_dir();
+    const bool fits = (int64_t)(lv.n_rows + 1) / 2 <= (int64_t)kPartDoubles;
+    if (fits && lv.sym) {
+        launch_spmv_dot_sym(h->s, lv.n_rows, P<double>::sym(lv), x, y, h->part, out, rev);
+        return;
+    }
+    if (fits && launch_spmv_dot(h->s, lv.n_rows, lv.np, lv.rp, lv.ci, lv.A64, x, y, h->part,
+                                out, rev))
+        return;
+    if (lv.sym)
+        launch_spmv_sym<double>(h->s, SPMV_AX, lv.n_rows, P<double>::sym(lv), x, nullptr, y, 0,
+                                rev);
+    else
+        launch_spmv<double>(h->s, SPMV_AX, lv.n_rows, lv.np, lv.rp, lv.ci, lv.A64, x, nullptr, y,
+                            0, rev);
+    launch_dot(h->s, lv.len(), x, y, h->part, out);
+}
+
+template <typename T>
+void xdg::level_jacobi(xdg_handle* h, Level& lv, bool first, const T* b, const T* xin,
+                       T* xout) {
+    const bool rev = lv.next_dir();
+    const T om = (T)h->opt.omega;
+    if (lv.sym && !first)
+        launch_jacobi_sym<T>(h->s, lv.n_cells, lv.cp, P<T>::sym(lv), lv.doff, P<T>::D(lv), b, xin,
+                             xout, om, rev);
+    else
+        launch_jacobi<T>(h->s, first, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv),
+                         lv.doff, P<T>::D(lv), b, xin, xout, om, rev);
+}
+template void xdg::level_jacobi<double>(xdg_handle*, Level&, bool, const double*, const double*,
+                                        double*);
+template void xdg::level_jacobi<float>(xdg_handle*, Level&, bool, const float*, const float*,
+                                       float*);
+
+// ---------------------------------------------------------------------------
 // V-cycle (templated on the storage precision of levels above the coarsest)
 
 template <typename T>
@@ -240,16 +307,13 @@ static void smooth_from_zero(xdg_handle* h, Level& lv, int sweeps) {
     T* b = P<T>::b(lv);
     T*& x = P<T>::x(lv);
     T*& y = P<T>::y(lv);
-    const T om = (T)h->opt.omega;
     if (sweeps <= 0) {
         launch_fill_zero<T>(h->s, lv.len(), x);
         return;
     }
-    launch_jacobi<T>(h->s, true, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv), lv.doff,
-                     P<T>::D(lv), b, nullptr, x, om, lv.next_dir());
+    xdg::level_jacobi<T>(h, lv, true, b, nullptr, x);
     for (int k = 1; k < sweeps; ++k) {
-        launch_jacobi<T>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv),
-                         lv.doff, P<T>::D(lv), b, x, y, om, lv.next_dir());
+        xdg::level_jacobi<T>(h, lv, false, b, x, y);
         std::swap(x, y);
     }
 }
@@ -264,8 +328,7 @@ static void smooth_more(xdg_handle* h, Level& lv, int sweeps) {
     T*& x = P<T>::x(lv);
     T*& y = P<T>::y(lv);
     for (int k = 0; k < sweeps; ++k) {
-        launch_jacobi<T>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, P<T>::A(lv),
-                         lv.doff, P<T>::D(lv), b, x, y, (T)h->opt.omega, lv.next_dir());
+        xdg::level_jacobi<T>(h, lv, false, b, x, y);
         std::swap(x, y);
     }
 }
@@ -302,11 +365,9 @@ static void vcycle(xdg_handle* h, int l) {
         smooth_from_zero<T>(h, f, h->opt.nu_pre);
     }
     if (f.t_kind == XDG_T_PTRUNC) {
-        launch_spmv<T>(h->s, SPMV_RESID_TRUNC, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f),
-                       P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np, f.next_dir());
+        xdg::level_spmv<T>(h, f, SPMV_RESID_TRUNC, P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np);
     } else {
-        launch_spmv<T>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, P<T>::A(f), P<T>::x(f),
-                       P<T>::b(f), P<T>::r(f), 0, f.next_dir());
+        xdg::level_spmv<T>(h, f, SPMV_RESID, P<T>::x(f), P<T>::b(f), P<T>::r(f), 0);
         launch_restrict_dense<T>(h->s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi, f.ridx,
                                  P<T>::R(f), P<T>::r(f), P<T>::b(c), P<T>::y(f));
     }
@@ -458,6 +519,41 @@ extern "C" void xdg_destroy(xdg_handle* h) {
     delete h;
 }
 
+// Row lists of the symmetric storage (SymRows): the upper blocks of every
+// row (their indices among all blocks in ufull) and, for every lower block
+// (i, j), the index of the stored (j, i).  False if some (i, j) has no (j, i).
+// Every row holds its diagonal block (checked before).
+struct SymLists {
+    std::vector<int> urp, uci, ufull, lrp, lci, lidx;
+};
+static bool sym_lists(int n, const int32_t* rp, const int32_t* ci, SymLists& o) {
+    o.urp.assign(n + 1, 0);
+    o.lrp.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        for (int b = rp[i]; b < rp[i + 1]; ++b)
+            if (ci[b] >= i) {
+                o.uci.push_back(ci[b]);
+                o.ufull.push_back(b);
+            }
+        o.urp[i + 1] = (int)o.uci.size();
+    }
+    for (int i = 0; i < n; ++i) {
+        for (int b = rp[i]; b < rp[i + 1]; ++b) {
+            const int j = ci[b];
+            if (j >= i) continue;
+            const auto first = o.uci.begin() + o.urp[j], last = o.uci.begin() + o.urp[j + 1];
+            const auto it = std::lower_bound(first, last, i);     // columns sorted per row
+            if (it == last || *it != i) return false;
+            o.lci.push_back(j);
+            o.lidx.push_back((int)(it - o.uci.begin()));
+        }
+        o.lrp[i + 1] = (int)o.lci.size();
+    }
+    // every lower block has its distinct stored mirror; the counts match only
+    // if every off-diagonal upper block (one diagonal block per row) has one too
+    return o.lci.size() + (size_t)n == o.uci.size();
+}
+
 static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
                        const xdg_transfer* T, const xdg_options* opt) {
     // -- validation -----------------------------------------------------
@@ -485,6 +581,13 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     if (opt->krylov == XDG_CG && opt->nu_pre != opt->nu_post)
         return fail(XDG_EINVAL, "xdg_create: CG needs nu_pre == nu_post (symmetric V-cycle)");
     if (opt->nrhs == kNrhs) CHK(mrhs_validate(opt, A0->np, T, n_levels));
+    if (opt->symmetric != 0 && opt->symmetric != 1)
+        return fail(XDG_EINVAL, "xdg_create: symmetric must be 0 or 1");
+    SymLists sl;
+    const bool use_sym = opt->symmetric == 1 && opt->nrhs == 1 && A0->np == kSymNp;
+    if (use_sym && !sym_lists(A0->n_rows, A0->row_ptr, A0->col_idx, sl))
+        return fail(XDG_EINVAL, "xdg_create: symmetric storage needs a symmetric block pattern "
+                                "(a block (i, j) without (j, i)); set symmetric = 0");
     int nr = A0->n_rows, npf = A0->np;
     for (int t = 0; t < n_levels - 1; ++t) {
         const xdg_transfer& tr = T[t];
@@ -543,6 +646,18 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     CHK(h->upload(&L0.ci, L0.h_ci.data(), L0.h_ci.size()));
     CHK(h->alloc(&L0.A64, (size_t)L0.nnzb * L0.np * L0.np));
     CHK(setup_cells(h, L0, A0->cell_ptr, A0->n_cells));
+    if (use_sym) {
+        L0.sym = true;
+        L0.nnzb_u = (int64_t)sl.uci.size();
+        CHK(h->upload(&L0.urp, sl.urp.data(), sl.urp.size()));
+        CHK(h->upload(&L0.uci, sl.uci.data(), sl.uci.size()));
+        CHK(h->upload(&L0.ufull, sl.ufull.data(), sl.ufull.size()));
+        CHK(h->upload(&L0.lrp, sl.lrp.data(), sl.lrp.size()));
+        CHK(h->upload(&L0.lci, sl.lci.data(), sl.lci.size()));
+        CHK(h->upload(&L0.lidx, sl.lidx.data(), sl.lidx.size()));
+        CHK(h->alloc(&L0.As64, (size_t)L0.nnzb_u * L0.np * L0.np));
+        if (h->mixed) CHK(h->alloc(&L0.As32, (size_t)L0.nnzb_u * L0.np * L0.np));
+    }
     for (int t = 0; t < n_levels - 1; ++t) {
         Level& f = h->L[t];
         Level& c = h->L[t + 1];
@@ -611,7 +726,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
         Level& lv = h->L[l];
         CHK(h->alloc(&lv.D64, lv.dsize));
         if (h->mixed) {
-            CHK(h->alloc(&lv.A32, (size_t)lv.nnzb * lv.np * lv.np));
+            if (!lv.sym) CHK(h->alloc(&lv.A32, (size_t)lv.nnzb * lv.np * lv.np));
             CHK(h->alloc(&lv.D32, lv.dsize));
         }
     }
@@ -708,7 +823,7 @@ extern "C" int xdg_spmv(xdg_handle* h, int32_t level, const double* x, double* y
                                     "level 0 only (xdg_spmm with XDG_MIXED for coarser levels)");
         return mrhs_spmm(h, 0, XDG_FP64, x, y);
     }
-    launch_spmv<double>(h->s, SPMV_AX, lv.n_rows, lv.np, lv.rp, lv.ci, lv.A64, x, nullptr, y, 0);
+    xdg::level_spmv<double>(h, lv, SPMV_AX, x, nullptr, y, 0);
     HIPCHK(hipGetLastError());
     return XDG_OK;
 }
@@ -721,8 +836,7 @@ extern "C" int xdg_smooth(xdg_handle* h, int32_t level, const double* b, double*
     Level& lv = h->L[level];
     reset_dirs(h);
     for (int k = 0; k < sweeps; ++k) {
-        launch_jacobi<double>(h->s, false, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64,
-                              lv.doff, lv.D64, b, x, lv.y64, h->opt.omega, lv.next_dir());
+        xdg::level_jacobi<double>(h, lv, false, b, x, lv.y64);
         HIPCHK(hipMemcpyAsync(x, lv.y64, lv.len() * sizeof(double), hipMemcpyDeviceToDevice,
                               h->s));
     }
@@ -790,8 +904,7 @@ static int read_scalars(xdg_handle* h, int first, int count) {
 
 static int true_relres(xdg_handle* h, const double* b, const double* x, double* out) {
     Level& f = h->L[0];
-    launch_spmv<double>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->w, 0,
-                        f.next_dir());
+    xdg::level_spmv<double>(h, f, SPMV_RESID, x, b, h->w, 0);
     launch_dot(h->s, f.len(), h->w, h->w, h->part, h->scal + S_RR);
     launch_dot(h->s, f.len(), b, b, h->part, h->scal + S_BB);
     CHK(read_scalars(h, S_BB, 2));
@@ -812,8 +925,7 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
     Level& f = h->L[0];
     const int64_t n = f.len();
     hipStream_t s = h->s;
-    launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0,
-                        f.next_dir());
+    xdg::level_spmv<double>(h, f, SPMV_RESID, x, b, h->r, 0);
     launch_dot(s, n, b, b, h->part, h->scal + S_BB);
     launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
     CHK(read_scalars(h, S_BB, 2));
@@ -839,14 +951,7 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
     for (int k = 1; k <= h->opt.maxit; ++k) {
         // q = A p with p . q formed in the product's epilogue where the block
         // size allows, and r . r formed in the update of x and r
-        const bool fits = (int64_t)(f.n_rows + 1) / 2 <= (int64_t)kPartDoubles;
-        const bool rev = f.next_dir();
-        if (!fits || !launch_spmv_dot(s, f.n_rows, f.np, f.rp, f.ci, f.A64, h->p, h->q, h->part,
-                                      h->scal + S_PQ, rev)) {
-            launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, h->p, nullptr,
-                                h->q, 0, rev);
-            launch_dot(s, n, h->p, h->q, h->part, h->scal + S_PQ);
-        }
+        xdg::level_spmv_dot(h, f, h->p, h->q, h->scal + S_PQ);
         if (flex) launch_dot(s, n, h->p, h->r, h->part, h->scal + cur);   // alpha numerator
         launch_cg_update_xr_dot(s, n, h->scal, cur, S_PQ, S_RR, h->p, h->q, x, h->r, h->part);
         CHK(read_scalars(h, S_RR, 2));
@@ -895,8 +1000,7 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
     bool first = true;
     for (;;) {
         // true FP64 residual (the refinement step)
-        launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->r, 0,
-                            f.next_dir());
+        xdg::level_spmv<double>(h, f, SPMV_RESID, x, b, h->r, 0);
         launch_dot(s, n, h->r, h->r, h->part, h->scal + S_RR);
         CHK(read_scalars(h, S_RR, 1));
         const double beta = std::sqrt(h->h_scal[S_RR]);
@@ -920,8 +1024,7 @@ static int solve_fgmres(xdg_handle* h, const double* b, double* x, double* hist,
             double* zj = h->Z + (int64_t)j * n;
             double* vn = h->V + (int64_t)(j + 1) * n;
             CHK(apply_precond(h, vj, zj));
-            launch_spmv<double>(s, SPMV_AX, f.n_rows, f.np, f.rp, f.ci, f.A64, zj, nullptr, vn, 0,
-                                f.next_dir());
+            xdg::level_spmv<double>(h, f, SPMV_AX, zj, nullptr, vn, 0);
             // CGS2
             launch_multidot(s, n, j + 1, h->V, vn, h->part, h->scal + S_H);
             launch_multi_axpy_neg(s, n, j + 1, h->V, h->scal + S_H, vn);
@@ -1214,6 +1317,7 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
         const int* bl = h->d_stage + boff[t];
         if (t == 0) {
             launch_transpose_list(s, (int)bcnt[t], bl, lv.np, val_dev, lv.A64);
+            sym_refresh(h, lv);
         } else {
             Level& f = h->L[t - 1];
             if (f.t_kind == XDG_T_PTRUNC)
@@ -1234,13 +1338,8 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
         }
     }
     CHK(invert_coarsest(h, h->L[nl - 1]));
-    if (h->mixed) {
-        for (int l = 0; l + 1 < nl; ++l) {
-            Level& lv = h->L[l];
-            launch_convert<double, float>(s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
-            launch_convert<double, float>(s, lv.dsize, lv.D64, lv.D32);
-        }
-    }
+    if (h->mixed)
+        for (int l = 0; l + 1 < nl; ++l) convert_level32(h, h->L[l]);
     HIPCHK(hipGetLastError());
     return check_setup_error(h);   // synchronises: the stage may be reused afterwards
 }

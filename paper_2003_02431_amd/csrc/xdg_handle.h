@@ -75,6 +75,15 @@ struct Level {
     double* Ap64 = nullptr;
     float *bm = nullptr, *xm = nullptr, *ym = nullptr, *rm = nullptr;
     double *bm64 = nullptr, *xm64 = nullptr;
+    // symmetric storage (level 0 of single-column handles with kSymNp modes):
+    // the diagonal and upper blocks As64 / As32 (ufull: their indices among
+    // all blocks) and the row lists of SymRows
+    bool sym = false;
+    int64_t nnzb_u = 0;
+    int *urp = nullptr, *uci = nullptr, *lrp = nullptr, *lci = nullptr, *lidx = nullptr;
+    int* ufull = nullptr;
+    double* As64 = nullptr;
+    float* As32 = nullptr;
     // direction of the next streaming pass over this level's blocks
     // (alternates; reset at every public call so that results are repeatable)
     bool rev_next = false;
@@ -95,6 +104,12 @@ template <> struct P<double> {
     static double*& x(Level& l) { return l.x64; }
     static double*& y(Level& l) { return l.y64; }
     static double*& r(Level& l) { return l.r64; }
+    static SymRows<double> sym(Level& l) {
+        SymRows<double> m;
+        m.urp = l.urp; m.uci = l.uci; m.lrp = l.lrp; m.lci = l.lci; m.lidx = l.lidx;
+        m.A = l.As64;
+        return m;
+    }
 };
 template <> struct P<float> {
     static float* A(Level& l) { return l.A32; }
@@ -104,6 +119,12 @@ template <> struct P<float> {
     static float*& x(Level& l) { return l.x32; }
     static float*& y(Level& l) { return l.y32; }
     static float*& r(Level& l) { return l.r32; }
+    static SymRows<float> sym(Level& l) {
+        SymRows<float> m;
+        m.urp = l.urp; m.uci = l.uci; m.lrp = l.lrp; m.lci = l.lci; m.lidx = l.lidx;
+        m.A = l.As32;
+        return m;
+    }
 };
 
 }  // namespace xdg
@@ -198,6 +219,18 @@ int mrhs_smooth(xdg_handle* h, int level, const double* B, double* X, int sweeps
 int mrhs_vcycle(xdg_handle* h, const double* R, double* Z);
 int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap, int* iters,
                double* final_relres);
+}  // namespace xdg
+
+namespace xdg {
+// the level's operator on its storage (all blocks, or the symmetric upper
+// blocks); every call flips the level's streaming direction
+template <typename T>
+void level_spmv(xdg_handle* h, Level& lv, int mode, const T* x, const T* b, T* y, int npc);
+// y = M x and *out = x . y on level 0 (fused where the block size allows)
+void level_spmv_dot(xdg_handle* h, Level& lv, const double* x, double* y, double* out);
+// one damped block-Jacobi sweep (first: x_in = 0, the matrix is not read)
+template <typename T>
+void level_jacobi(xdg_handle* h, Level& lv, bool first, const T* b, const T* xin, T* xout);
 }  // namespace xdg
 
 namespace xdg {

@@ -58,6 +58,33 @@ bool launch_spmv_dot(hipStream_t s, int n_rows, int np, const int* rp, const int
                      const double* A, const double* x, double* y, double* partial, double* out,
                      bool rev = false);
 
+// Symmetric level matrix kept as its diagonal and upper blocks (column >= row):
+// row i's upper blocks are urp[i] .. urp[i+1]-1 (columns uci, column-major
+// blocks A, row by row); its lower blocks (i, j), j < i, are listed in
+// lrp[i] .. lrp[i+1]-1 with the column j (lci) and the index in A of the
+// stored block (j, i) (lidx), whose transpose they are.  Kernels exist for
+// kSymNp modes per block.
+constexpr int kSymNp = 20;
+template <typename T>
+struct SymRows {
+    const int *urp = nullptr, *uci = nullptr, *lrp = nullptr, *lci = nullptr, *lidx = nullptr;
+    const T* A = nullptr;
+};
+template <typename T>
+void launch_spmv_sym(hipStream_t s, int mode, int n_rows, const SymRows<T>& m, const T* x,
+                     const T* b, T* y, int npc, bool rev);
+void launch_spmv_dot_sym(hipStream_t s, int n_rows, const SymRows<double>& m, const double* x,
+                         double* y, double* partial, double* out, bool rev);
+// x_in given (not the first sweep from zero)
+template <typename T>
+void launch_jacobi_sym(hipStream_t s, int n_cells, const int* cp, const SymRows<T>& m,
+                       const int64_t* doff, const T* D, const T* b, const T* xin, T* xout,
+                       T omega, bool rev);
+// out[k] = in[idx[k]] for blocks of bs entries (converted to Tout)
+template <typename Tin, typename Tout>
+void launch_gather_blocks(hipStream_t s, int64_t n, int bs, const int* idx, const Tin* in,
+                          Tout* out);
+
 // ---- setup (k_setup.hip) -------------------------------------------------
 template <typename T>
 void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* in, T* out);

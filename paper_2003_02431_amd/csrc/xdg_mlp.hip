@@ -184,7 +184,7 @@ extern "C" int xdg_learned_pairs(xdg_handle* h, const double* b, const double* x
         return fail(XDG_EINVAL, "xdg_learned_pairs: bad cell selection");
     const int n_sel = (f.n_cells - cell0 + cell_step - 1) / cell_step;
     // residual of the iterate, then features and targets of the selected cells
-    launch_spmv<double>(h->s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, xk, b, h->w, 0);
+    xdg::level_spmv<double>(h, f, SPMV_RESID, xk, b, h->w, 0);
     launch_learned_features(h->s, n_sel, cell0, cell_step, f.cp, h->row_species, h->cell_geom,
                             f.doff, f.D64, h->w, xk, xs, h->opt.omega, clip, X, T);
     HIPCHK(hipGetLastError());

@@ -29,7 +29,7 @@ int om_rm(xdg_handle* h, int l, const double* z) {
     double* zk = h->omZ[l] + (int64_t)k * n;
     double* wk = h->omW[l] + (int64_t)k * n;
     HIPCHK(hipMemcpyAsync(zk, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_spmv<double>(s, SPMV_AX, lv.n_rows, lv.np, lv.rp, lv.ci, lv.A64, zk, nullptr, wk, 0);
+    xdg::level_spmv<double>(h, lv, SPMV_AX, zk, nullptr, wk, 0);
     if (k > 0) {
         for (int pass = 0; pass < 2; ++pass) {
             double* beta = h->scal + (pass == 0 ? O_B1 : O_B2);
@@ -155,7 +155,7 @@ int solve_orthomg(xdg_handle* h, const double* b, double* x, double* hist, int c
     } restore{h, h->omX[0]};
     h->omX[0] = x;
     int rc = XDG_ENOCONV;
-    launch_spmv<double>(s, SPMV_RESID, f.n_rows, f.np, f.rp, f.ci, f.A64, x, b, h->omR[0], 0);
+    xdg::level_spmv<double>(h, f, SPMV_RESID, x, b, h->omR[0], 0);
     h->om_count[0] = 0;
     for (int k = 0;; ++k) {
         launch_dot(s, n, h->omR[0], h->omR[0], h->part, h->scal + O_RR);

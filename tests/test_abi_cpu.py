@@ -69,6 +69,23 @@ def test_create_rejects_bad_options():
         assert e.value.code == B.XDG_EINVAL
 
 
+def test_symmetric_storage_needs_a_symmetric_pattern():
+    """Symmetric storage (20-mode blocks) reads lower blocks as transposes of
+    the stored upper ones, so every block (i, j) needs its (j, i); the check is
+    part of the validation, before any device call."""
+    from paper_2003_02431_amd import binding as B
+    rp = np.array([0, 2, 3], np.int32)           # (0,0) (0,1) / (1,1): no (1,0)
+    ci = np.array([0, 1, 1], np.int32)
+    val = np.tile(np.eye(20), (3, 1, 1))
+    cp = np.array([0, 1, 2], np.int32)
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_create(rp, ci, val, cp, [], B.options())
+    assert e.value.code == B.XDG_EINVAL and "symmetric" in str(e.value)
+    with pytest.raises(B.XdgError) as e:
+        B.xdg_create(rp, ci, val, cp, [], B.options(symmetric=2))
+    assert e.value.code == B.XDG_EINVAL and "symmetric" in str(e.value)
+
+
 def test_create_rejects_bad_transfer():
     from paper_2003_02431_amd import binding as B
     rp, ci, val, cp = _tiny()

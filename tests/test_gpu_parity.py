@@ -41,7 +41,7 @@ def _make(name):
         return problems.c1()
     if name == "c2n8":
         return problems.c2(seed=3, n=8, hier=[("p", 1), ("h", 1)])
-    if name == "c2n16":
+    if name in ("c2n16", "c2n16gen"):
         return problems.c2(seed=1, n=16)
     if name == "c2n8hp":
         # aggregation level at the fine degree (20 coarse modes per block)
@@ -66,12 +66,15 @@ def _case(name, torch):
         _log(f"[gpu-parity] building case {name}")
         pr = _make(name)
         H = mg.hierarchy_of(pr)
-        S = B.Solver(pr, B.options(rtol=1e-10, maxit=600))
+        # "gen": the level-0 solve kernels read every block (symmetric = 0);
+        # otherwise 20-mode levels use the symmetric (upper-block) storage
+        sym = 0 if name.endswith("gen") else 1
+        S = B.Solver(pr, B.options(rtol=1e-10, maxit=600, symmetric=sym))
         _STATE[name] = (pr, H, S)
     return _STATE[name]
 
 
-CASES = ["c1", "c2n8", "c2n16", "c4n8p4", "c2n8hp", "c2n16h3p1"]
+CASES = ["c1", "c2n8", "c2n16", "c2n16gen", "c4n8p4", "c2n8hp", "c2n16h3p1"]
 
 
 def _rel(a, b):
