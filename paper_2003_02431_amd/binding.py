@@ -10,6 +10,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch before libxdg: the process must hold one HIP runtime, and libxdg's
+# dependency has to resolve to the one torch brings (loaded the other way
+# round, two runtimes coexist and the library's finds no device)
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxdg.so")
 

@@ -482,9 +482,11 @@ __global__ __launch_bounds__(256) void k_bsr_spmv_sym(int n_rows, const int* __r
     }
 }
 
-// Damped block-Jacobi sweep (x_in given) on the symmetric storage: one wave
-// per cell as in k_jacobi, each row's residual formed from its upper and
-// lower streams.
+// Damped block-Jacobi sweep (x_in given) on the symmetric storage: two waves
+// per cell, the first streams the upper blocks of the cell's rows, the second
+// the lower (transposed) ones; the row sums meet in LDS, the residual
+// b - (upper + lower) is formed in a fixed order, and the first wave applies
+// the cell-block inverse.
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void k_jacobi_sym(int n_cells, const int* __restrict__ cell_ptr,
                                                     const int* __restrict__ urp,
@@ -501,52 +503,59 @@ __global__ __launch_bounds__(256) void k_jacobi_sym(int n_cells, const int* __re
     using R = RowCfg<T, NP, true>;
     using S = SymCfg<T, NP>;
     constexpr int V = R::VEC;
-    __shared__ T res[4][kMaxCell];
-    __shared__ T lo[4][NP];
+    __shared__ T up[2][kMaxCell];
+    __shared__ T lo[2][kMaxCell];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int cell0 = uniform(blockIdx.x * 4 + w);
-    if (cell0 >= n_cells) return;
+    const int c2 = w >> 1;
+    const int half = w & 1;
+    const int cell0 = uniform(blockIdx.x * 2 + c2);
+    const bool valid = cell0 < n_cells;
     const int cell = rev ? n_cells - 1 - cell0 : cell0;
-    const int r0 = uniform(cell_ptr[cell]), r1 = uniform(cell_ptr[cell + 1]);
+    int r0 = 0, r1 = 0;
+    if (valid) {
+        r0 = uniform(cell_ptr[cell]);
+        r1 = uniform(cell_ptr[cell + 1]);
+    }
     const int nc = (r1 - r0) * NP;
-    const int q = lane % S::L, cl = lane / S::L;
-    for (int row = r0; row < r1; ++row) {
-        const int64_t ob = (int64_t)row * NP;
-        T acc[V];
+    if (!half) {
+        for (int row = r0; row < r1; ++row) {
+            T acc[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = 0;
-        const int b0 = uniform(urp[row]);
-        row_stream<T, NP, true>(b0, uniform(urp[row + 1]) - b0, uci, As, xin, lane, acc);
-        reduce_groups<T, V>(acc, R::L, R::C);
-        T lacc[S::KT];
+            for (int v = 0; v < V; ++v) acc[v] = 0;
+            const int b0 = uniform(urp[row]);
+            row_stream<T, NP, true>(b0, uniform(urp[row + 1]) - b0, uci, As, xin, lane, acc);
+            reduce_groups<T, V>(acc, R::L, R::C);
+            if (lane < R::L) {
 #pragma unroll
-        for (int m = 0; m < S::KT; ++m) lacc[m] = 0;
-        const int l0 = uniform(lrp[row]);
-        lower_stream<T, NP>(l0, uniform(lrp[row + 1]) - l0, lci, lidx, As, xin, lane, lacc);
-        if (q == 0 && cl < S::CT) {
-#pragma unroll
-            for (int m = 0; m < S::KT; ++m) lo[w][m * S::CT + cl] = lacc[m];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < R::L) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int r = lane * V + v;
-                res[w][(row - r0) * NP + r] = b[ob + r] - (acc[v] + lo[w][r]);
+                for (int v = 0; v < V; ++v) up[c2][(row - r0) * NP + lane * V + v] = acc[v];
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        const int q = lane % S::L, cl = lane / S::L;
+        for (int row = r0; row < r1; ++row) {
+            T lacc[S::KT];
+#pragma unroll
+            for (int m = 0; m < S::KT; ++m) lacc[m] = 0;
+            const int l0 = uniform(lrp[row]);
+            lower_stream<T, NP>(l0, uniform(lrp[row + 1]) - l0, lci, lidx, As, xin, lane, lacc);
+            if (q == 0 && cl < S::CT) {
+#pragma unroll
+                for (int m = 0; m < S::KT; ++m) lo[c2][(row - r0) * NP + m * S::CT + cl] = lacc[m];
+            }
+        }
     }
-    const T* Dc = D + doff[cell];
+    __syncthreads();
+    if (half || !valid) return;
     const int64_t base = (int64_t)r0 * NP;
+    for (int e = lane; e < nc; e += 64) up[c2][e] = b[base + e] - (up[c2][e] + lo[c2][e]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const T* Dc = D + doff[cell];
     if (nc <= 64 * V) {
         T acc[V];
-        dense_apply<T, V>(Dc, nc, res[w], lane, acc);
+        dense_apply<T, V>(Dc, nc, up[c2], lane, acc);
         if (lane < nc / V) {
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -557,7 +566,7 @@ __global__ __launch_bounds__(256) void k_jacobi_sym(int n_cells, const int* __re
     } else {
         for (int o = lane; o < nc; o += 64) {
             T acc = 0;
-            for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * res[w][c];
+            for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * up[c2][c];
             xout[base + o] = xin[base + o] + omega * acc;
         }
     }
@@ -1008,7 +1017,7 @@ template <typename T>
 void launch_jacobi_sym(hipStream_t s, int n_cells, const int* cp, const SymRows<T>& m,
                        const int64_t* doff, const T* D, const T* b, const T* xin, T* xout,
                        T omega, bool rev) {
-    k_jacobi_sym<T, kSymNp><<<nblk(n_cells, 4), 256, 0, s>>>(n_cells, cp, m.urp, m.uci, m.A,
+    k_jacobi_sym<T, kSymNp><<<nblk(n_cells, 2), 256, 0, s>>>(n_cells, cp, m.urp, m.uci, m.A,
                                                              m.lrp, m.lci, m.lidx, doff, D, b,
                                                              xin, xout, omega, rev ? 1 : 0);
 }

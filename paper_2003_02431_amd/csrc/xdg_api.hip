@@ -322,15 +322,22 @@ void xdg::smooth_from_zero_fp64(xdg_handle* h, Level& lv, int sweeps) {
     smooth_from_zero<double>(h, lv, sweeps);
 }
 
+// out != nullptr: the last sweep writes there instead (x keeps the previous
+// iterate)
 template <typename T>
-static void smooth_more(xdg_handle* h, Level& lv, int sweeps) {
+static void smooth_more(xdg_handle* h, Level& lv, int sweeps, T* out = nullptr) {
     T* b = P<T>::b(lv);
     T*& x = P<T>::x(lv);
     T*& y = P<T>::y(lv);
     for (int k = 0; k < sweeps; ++k) {
+        if (out && k == sweeps - 1) {
+            xdg::level_jacobi<T>(h, lv, false, b, x, out);
+            return;
+        }
         xdg::level_jacobi<T>(h, lv, false, b, x, y);
         std::swap(x, y);
     }
+    if (out) (void)hipMemcpyAsync(out, x, lv.len() * sizeof(T), hipMemcpyDeviceToDevice, h->s);
 }
 
 template <typename T>
@@ -347,12 +354,15 @@ void coarse_solve<float>(xdg_handle* h, Level& lv) {
     launch_convert<double, float>(h->s, lv.len(), lv.x64, lv.x32);
 }
 
-// input: P<T>::b(L[l]); output: P<T>::x(L[l])
+// input: P<T>::b(L[l]); output: P<T>::x(L[l]), or `out` when given
 template <typename T>
-static void vcycle(xdg_handle* h, int l) {
+static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
     Level& f = h->L[l];
     if (l == (int)h->L.size() - 1) {
         coarse_solve<T>(h, f);
+        if (out)
+            (void)hipMemcpyAsync(out, P<T>::x(f), f.len() * sizeof(T), hipMemcpyDeviceToDevice,
+                                 h->s);
         return;
     }
     Level& c = h->L[l + 1];
@@ -377,7 +387,7 @@ static void vcycle(xdg_handle* h, int l) {
     else
         launch_prolong_dense<T>(h->s, f.n_rows, f.np, c.np, f.parent, f.ridx, P<T>::R(f), P<T>::x(c),
                                 P<T>::x(f));
-    smooth_more<T>(h, f, h->opt.nu_post);
+    smooth_more<T>(h, f, h->opt.nu_post, out);
 }
 
 // every public call starts its streaming passes in ascending order
@@ -393,10 +403,17 @@ static int apply_precond(xdg_handle* h, const double* r, double* z) {
         launch_convert<double, float>(h->s, n, r, f.b32);
         vcycle<float>(h, 0);
         launch_convert<float, double>(h->s, n, f.x32, z);
-    } else {
+    } else if (r == z) {
         HIPCHK(hipMemcpyAsync(f.b64, r, n * sizeof(double), hipMemcpyDeviceToDevice, h->s));
         vcycle<double>(h, 0);
         HIPCHK(hipMemcpyAsync(z, f.x64, n * sizeof(double), hipMemcpyDeviceToDevice, h->s));
+    } else {
+        // the cycle reads level 0's right-hand side from r (only read there)
+        // and its last sweep writes z
+        double* own_b = f.b64;
+        f.b64 = const_cast<double*>(r);
+        vcycle<double>(h, 0, z);
+        f.b64 = own_b;
     }
     HIPCHK(hipGetLastError());
     return XDG_OK;
