@@ -69,6 +69,11 @@ def spmv_bytes(pr, word=8, sym=False):
     return nu * npm * npm * word + 4 * nu + 8 * (rows + 1) + 8 * nl + vec
 
 
+def problems_c_eta():
+    from xdg_inputs import problems
+    return problems.C_ETA_DEFAULT
+
+
 def uses_symmetric(pr):
     """The library keeps level 0 in symmetric storage for 20-mode blocks
     (single column, option symmetric = 1, the default of the binding)."""
@@ -152,20 +157,21 @@ class _Cached:
         return pr
 
 
-def load_problem(n, seed, workload="c2", p=3, hier="p1h"):
+def load_problem(n, seed, workload="c2", p=3, hier="p1h", c_eta=None):
     """Generate the workload (or reuse a copy saved by an earlier run of this
     benchmark in the same session when XDG_BENCH_CACHE names a directory).
     c5: the 64^3 ellipsoid family with one right-hand side plus the learned
     smoother's cell features."""
     from xdg_inputs import problems
     cache = os.environ.get("XDG_BENCH_CACHE")
-    tag = {"c2": f"c2_n{n}_s{seed}_{hier}", "c4": f"c4_n{n}_p{p}_s{seed}",
-           "c5": f"c5_n{n}_p{p}_s{seed}"}[workload]
+    tag = {"c2": f"c2_n{n}_s{seed}_{hier}" + (f"_eta{c_eta:g}" if c_eta else ""),
+           "c4": f"c4_n{n}_p{p}_s{seed}", "c5": f"c5_n{n}_p{p}_s{seed}"}[workload]
     path = os.path.join(cache, tag + ".npz") if cache else None
     if path and os.path.exists(path):
         return _Cached.load(path)
     if workload == "c2":
-        pr = problems.c2(seed=seed, n=n, hier=problems.hierarchy(hier, n, 3))
+        kw = {"c_eta": c_eta} if c_eta else {}
+        pr = problems.c2(seed=seed, n=n, hier=problems.hierarchy(hier, n, 3), **kw)
     elif workload == "c4":
         pr = problems.c4(seed=seed, n=n, p=p, nrhs=16, verbose=True)
     else:
@@ -446,6 +452,8 @@ def main():
     ap.add_argument("--hier", default="p1h", choices=["p1h", "h3p1", "hp", "h2p"],
                     help="coarse-level sequence of the 32^3 workload (xdg_inputs.problems."
                          "hierarchy)")
+    ap.add_argument("--c-eta", type=float, default=None,
+                    help="penalty constant C of the SIP penalty (default: the generator's 1)")
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--profile-spmv", action="store_true",
                     help="only launch the level-0 SpMV 20 times and a plain copy (counters)")
@@ -476,7 +484,7 @@ def main():
     torch.cuda.set_device(0)
     log(f"[bench] generating c2 workload n={args.n} seed={args.seed}")
     t0 = time.time()
-    pr = load_problem(args.n, args.seed, hier=args.hier)
+    pr = load_problem(args.n, args.seed, hier=args.hier, c_eta=args.c_eta)
     log(f"[bench] generated rows={pr.n_rows} nnzb={pr.col_idx.size} in {time.time() - t0:.1f}s")
 
     def opts(**kw):
@@ -762,7 +770,7 @@ def main():
                                                              for T in pr.transfers],
                    "krylov": "CG",
                    "smoother": f"block-Jacobi {args.nu}+{args.nu} omega={args.omega}",
-                   "seed": args.seed},
+                   "c_eta": args.c_eta or problems_c_eta(), "seed": args.seed},
         "iters_to_1e-8": int(np.median(its)),
         "setup_ms": round(setup_ms, 3),
         "time_to_1e-10_s": round(dt10, 6),

@@ -147,12 +147,12 @@ def hierarchy(kind, n, p):
     raise KeyError(kind)
 
 
-def c2(seed=0, n=32, p=3, verbose=False, hier=None):
+def c2(seed=0, n=32, p=3, verbose=False, hier=None, c_eta=C_ETA_DEFAULT):
     g = _rng.problem_rng(seed)
     ctr = _rng.sphere_jitter(g, 0.05)
     hier = hier or hierarchy("p1h", n, p)
     return build(f"c2_3d_p{p}_n{n}_s{seed}", 3, n, p, Quadric.sphere(ctr, 0.6), (1.0, 1000.0),
-                 hierarchy=hier, rhs="random", rng=g, verbose=verbose)
+                 hierarchy=hier, rhs="random", rng=g, verbose=verbose, c_eta=c_eta)
 
 
 def c4(seed=0, n=64, p=3, nrhs=16, verbose=False):
