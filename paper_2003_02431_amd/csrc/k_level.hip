@@ -157,14 +157,16 @@ __device__ __forceinline__ T row_times_x_rt(int beg, int end, const int* __restr
 // grid (measured 131.4 -> 127.9 us at 32^3 p=3).
 // MODE SPMV_AX_DOT (Np >= 16): y = A x and, per workgroup, the partial inner
 // product x . y of its two rows (fixed order: lanes, then row 0 + row 1) in
-// dpart[blockIdx.x].
+// dpart[blockIdx.x].  MODE SPMV_RESID_TRUNC with yfull != nullptr (Np >= 16)
+// also keeps the whole residual b - A x in yfull.
 template <typename T, int NP, int MODE>
 __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const int* __restrict__ rp,
                                                   const int* __restrict__ ci,
                                                   const T* __restrict__ A,
                                                   const T* __restrict__ x,
                                                   const T* __restrict__ b, T* __restrict__ y,
-                                                  int npc, double* __restrict__ dpart, int rev) {
+                                                  int npc, double* __restrict__ dpart, int rev,
+                                                  T* __restrict__ yfull) {
     const int lane = threadIdx.x & 63;
     if constexpr (NP >= 16) {
         using R = RowCfg<T, NP, true>;
@@ -201,7 +203,11 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int n_rows, int np_rt, const i
                 const int64_t o = (int64_t)row * NP + r;
                 if (MODE == SPMV_AX || MODE == SPMV_AX_DOT) y[o] = sum;
                 else if (MODE == SPMV_RESID) y[o] = b[o] - sum;
-                else if (r < npc) y[(int64_t)row * npc + r] = b[o] - sum;
+                else {
+                    const T res = b[o] - sum;
+                    if (r < npc) y[(int64_t)row * npc + r] = res;
+                    if (yfull) yfull[o] = res;
+                }
                 if (MODE == SPMV_AX_DOT) dot += (double)x[o] * (double)sum;
             }
         }
@@ -424,7 +430,7 @@ __global__ __launch_bounds__(256) void k_bsr_spmv_sym(int n_rows, const int* __r
                                                       const T* __restrict__ x,
                                                       const T* __restrict__ b, T* __restrict__ y,
                                                       int npc, double* __restrict__ dpart,
-                                                      int rev) {
+                                                      int rev, T* __restrict__ yfull) {
     using R = RowCfg<T, NP, true>;
     using S = SymCfg<T, NP>;
     __shared__ T part[2][NP];
@@ -470,7 +476,11 @@ __global__ __launch_bounds__(256) void k_bsr_spmv_sym(int n_rows, const int* __r
             const int64_t o = (int64_t)row * NP + r;
             if (MODE == SPMV_AX || MODE == SPMV_AX_DOT) y[o] = sum;
             else if (MODE == SPMV_RESID) y[o] = b[o] - sum;
-            else if (r < npc) y[(int64_t)row * npc + r] = b[o] - sum;
+            else {
+                const T res = b[o] - sum;
+                if (r < npc) y[(int64_t)row * npc + r] = res;
+                if (yfull) yfull[o] = res;
+            }
             if (MODE == SPMV_AX_DOT) dot += (double)x[o] * (double)sum;
         }
     }
@@ -568,6 +578,114 @@ __global__ __launch_bounds__(256) void k_jacobi_sym(int n_cells, const int* __re
             T acc = 0;
             for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * up[c2][c];
             xout[base + o] = xin[base + o] + omega * acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// First post-smoothing sweep after a p-coarse correction, from the residual
+// the pre-smoothing pass kept.  With x2 = x1 + P e (P the p-prolongation:
+// e fills the leading NC modes of every block row) and r1 = b - M x1,
+//   b - M x2 = r1 - (M P) e,
+// and M P consists of the leading NC columns of every block -- with blocks
+// column-major, the first NP*NC entries of each, stored contiguously as AP.
+// So the sweep
+//   x_out = x2 + omega D^-1 (r1 - (M P) e)
+// streams NP*NC instead of NP*NP entries per block and needs no separate
+// prolongation.  One wave per cell as k_jacobi; the AP blocks of a row are
+// one contiguous stream of NP x NC column-major blocks.
+template <typename T, int NP, int NC>
+__device__ __forceinline__ void row_stream_nc(int b0, int nb, const int* __restrict__ ci,
+                                              const T* __restrict__ AP, const T* __restrict__ e,
+                                              int lane, T (&acc)[RowCfg<T, NP, true>::VEC]) {
+    using R = RowCfg<T, NP, true>;
+    constexpr int V = R::VEC;
+    const int q = lane % R::L;
+    const int cl = lane / R::L;
+    const bool act = cl < R::C;
+    const int colreg = lane < nb ? ci[b0 + lane] : 0;
+    const T* Ar = AP + (int64_t)b0 * (NP * NC);
+    const int E = nb * (NP * NC);
+    const int off = cl * NP + q * V;
+    for (int base = 0; base < E; base += R::CH) {
+        const int ee = base + off;
+        const bool ok = act && ee < E;
+        const int xi = ee / NP;            // column within the row's stream
+        const int bb = xi / NC;            // block within the row
+        int col = __shfl(colreg, bb & 63, 64);
+        if (ok) {
+            if (bb >= 64) col = ci[b0 + bb];
+            const T ev = e[(int64_t)col * NC + (xi - bb * NC)];
+            T a[V];
+            load_vec<T, V>(Ar + ee, a);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] += a[v] * ev;
+        }
+    }
+}
+
+template <typename T, int NP, int NC>
+__global__ __launch_bounds__(256) void k_jacobi_cc(int n_cells, const int* __restrict__ cell_ptr,
+                                                   const int* __restrict__ rp,
+                                                   const int* __restrict__ ci,
+                                                   const T* __restrict__ AP,
+                                                   const int64_t* __restrict__ doff,
+                                                   const T* __restrict__ D,
+                                                   const T* __restrict__ r1,
+                                                   const T* __restrict__ x1,
+                                                   const T* __restrict__ e,
+                                                   T* __restrict__ xout, T omega, int rev) {
+    using R = RowCfg<T, NP, true>;
+    constexpr int V = R::VEC;
+    __shared__ T res[4][kMaxCell];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int cell0 = uniform(blockIdx.x * 4 + w);
+    if (cell0 >= n_cells) return;
+    const int cell = rev ? n_cells - 1 - cell0 : cell0;
+    const int r0 = uniform(cell_ptr[cell]), r1_ = uniform(cell_ptr[cell + 1]);
+    const int nc = (r1_ - r0) * NP;
+    for (int row = r0; row < r1_; ++row) {
+        const int64_t ob = (int64_t)row * NP;
+        T acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0;
+        const int b0 = uniform(rp[row]);
+        row_stream_nc<T, NP, NC>(b0, uniform(rp[row + 1]) - b0, ci, AP, e, lane, acc);
+        reduce_groups<T, V>(acc, R::L, R::C);
+        if (lane < R::L) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int r = lane * V + v;
+                res[w][(row - r0) * NP + r] = r1[ob + r] - acc[v];
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const T* Dc = D + doff[cell];
+    const int64_t base = (int64_t)r0 * NP;
+    // x2 = x1 + P e at entry o of the cell (block row o / NP, mode o % NP)
+    auto x2 = [&](int o) -> T {
+        const int rr = o / NP, m = o - rr * NP;
+        return x1[base + o] + (m < NC ? e[(int64_t)(r0 + rr) * NC + m] : T(0));
+    };
+    if (nc <= 64 * V) {
+        T acc[V];
+        dense_apply<T, V>(Dc, nc, res[w], lane, acc);
+        if (lane < nc / V) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int o = lane * V + v;
+                xout[base + o] = x2(o) + omega * acc[v];
+            }
+        }
+    } else {
+        for (int o = lane; o < nc; o += 64) {
+            T acc = 0;
+            for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * res[w][c];
+            xout[base + o] = x2(o) + omega * acc;
         }
     }
 }
@@ -901,7 +1019,7 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 
 template <typename T, int MODE>
 static void spmv_np(hipStream_t s, int n_rows, int np, const int* rp, const int* ci, const T* A,
-                    const T* x, const T* b, T* y, int npc, int rev) {
+                    const T* x, const T* b, T* y, int npc, int rev, T* yfull) {
     dim3 g(nblk(n_rows, 4)), blk(256);
     dim3 gg(nblk(n_rows, 256 / kGS));
     switch (np) {
@@ -910,27 +1028,28 @@ static void spmv_np(hipStream_t s, int n_rows, int np, const int* rp, const int*
         XDG_NPG(1) XDG_NPG(3) XDG_NPG(4) XDG_NPG(6)
 #undef XDG_NPG
 #define XDG_NP(N) \
-    case N: k_bsr_spmv<T, N, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc, nullptr, rev); break;
+    case N: k_bsr_spmv<T, N, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc, nullptr, rev, nullptr); break;
         XDG_NP(10)
 #undef XDG_NP
 #define XDG_NP2(N)                                                                          \
     case N:                                                                                 \
         k_bsr_spmv<T, N, MODE><<<nblk(n_rows, 2), blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, \
-                                                                npc, nullptr, rev);         \
+                                                                npc, nullptr, rev, yfull);  \
         break;
         XDG_NP2(20) XDG_NP2(35)
 #undef XDG_NP2
-        default: k_bsr_spmv<T, 0, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc, nullptr, rev);
+        default: k_bsr_spmv<T, 0, MODE><<<g, blk, 0, s>>>(n_rows, np, rp, ci, A, x, b, y, npc, nullptr, rev, nullptr);
     }
 }
 
 template <typename T>
 void launch_spmv(hipStream_t s, int mode, int n_rows, int np, const int* rp, const int* ci,
-                 const T* A, const T* x, const T* b, T* y, int npc, bool rev) {
+                 const T* A, const T* x, const T* b, T* y, int npc, bool rev, T* yfull) {
     const int r = rev ? 1 : 0;
-    if (mode == SPMV_AX) spmv_np<T, SPMV_AX>(s, n_rows, np, rp, ci, A, x, b, y, npc, r);
-    else if (mode == SPMV_RESID) spmv_np<T, SPMV_RESID>(s, n_rows, np, rp, ci, A, x, b, y, npc, r);
-    else spmv_np<T, SPMV_RESID_TRUNC>(s, n_rows, np, rp, ci, A, x, b, y, npc, r);
+    if (mode == SPMV_AX) spmv_np<T, SPMV_AX>(s, n_rows, np, rp, ci, A, x, b, y, npc, r, nullptr);
+    else if (mode == SPMV_RESID)
+        spmv_np<T, SPMV_RESID>(s, n_rows, np, rp, ci, A, x, b, y, npc, r, nullptr);
+    else spmv_np<T, SPMV_RESID_TRUNC>(s, n_rows, np, rp, ci, A, x, b, y, npc, r, yfull);
 }
 
 // y = A x and *out = x . y (FP64, Np = 20 or 35: the product's epilogue forms
@@ -943,10 +1062,10 @@ bool launch_spmv_dot(hipStream_t s, int n_rows, int np, const int* rp, const int
     const int r = rev ? 1 : 0;
     if (np == 20)
         k_bsr_spmv<double, 20, SPMV_AX_DOT><<<nb, 256, 0, s>>>(n_rows, np, rp, ci, A, x, nullptr,
-                                                               y, 0, partial, r);
+                                                               y, 0, partial, r, nullptr);
     else if (np == 35)
         k_bsr_spmv<double, 35, SPMV_AX_DOT><<<nb, 256, 0, s>>>(n_rows, np, rp, ci, A, x, nullptr,
-                                                               y, 0, partial, r);
+                                                               y, 0, partial, r, nullptr);
     else
         return false;
     launch_dot_final(s, partial, (int)nb, out);
@@ -991,25 +1110,27 @@ void launch_jacobi(hipStream_t s, bool first, int n_cells, int np, const int* cp
 
 template <typename T, int MODE>
 static void spmv_sym_mode(hipStream_t s, int n_rows, const SymRows<T>& m, const T* x,
-                          const T* b, T* y, int npc, double* dpart, int rev) {
+                          const T* b, T* y, int npc, double* dpart, int rev, T* yfull) {
     k_bsr_spmv_sym<T, kSymNp, MODE><<<nblk(n_rows, 2), 256, 0, s>>>(
-        n_rows, m.urp, m.uci, m.A, m.lrp, m.lci, m.lidx, x, b, y, npc, dpart, rev);
+        n_rows, m.urp, m.uci, m.A, m.lrp, m.lci, m.lidx, x, b, y, npc, dpart, rev, yfull);
 }
 
 template <typename T>
 void launch_spmv_sym(hipStream_t s, int mode, int n_rows, const SymRows<T>& m, const T* x,
-                     const T* b, T* y, int npc, bool rev) {
+                     const T* b, T* y, int npc, bool rev, T* yfull) {
     const int r = rev ? 1 : 0;
-    if (mode == SPMV_AX) spmv_sym_mode<T, SPMV_AX>(s, n_rows, m, x, b, y, npc, nullptr, r);
+    if (mode == SPMV_AX)
+        spmv_sym_mode<T, SPMV_AX>(s, n_rows, m, x, b, y, npc, nullptr, r, nullptr);
     else if (mode == SPMV_RESID)
-        spmv_sym_mode<T, SPMV_RESID>(s, n_rows, m, x, b, y, npc, nullptr, r);
-    else spmv_sym_mode<T, SPMV_RESID_TRUNC>(s, n_rows, m, x, b, y, npc, nullptr, r);
+        spmv_sym_mode<T, SPMV_RESID>(s, n_rows, m, x, b, y, npc, nullptr, r, nullptr);
+    else spmv_sym_mode<T, SPMV_RESID_TRUNC>(s, n_rows, m, x, b, y, npc, nullptr, r, yfull);
 }
 
 void launch_spmv_dot_sym(hipStream_t s, int n_rows, const SymRows<double>& m, const double* x,
                          double* y, double* partial, double* out, bool rev) {
     const unsigned nb = nblk(n_rows, 2);
-    spmv_sym_mode<double, SPMV_AX_DOT>(s, n_rows, m, x, nullptr, y, 0, partial, rev ? 1 : 0);
+    spmv_sym_mode<double, SPMV_AX_DOT>(s, n_rows, m, x, nullptr, y, 0, partial, rev ? 1 : 0,
+                                       nullptr);
     launch_dot_final(s, partial, (int)nb, out);
 }
 
@@ -1020,6 +1141,22 @@ void launch_jacobi_sym(hipStream_t s, int n_cells, const int* cp, const SymRows<
     k_jacobi_sym<T, kSymNp><<<nblk(n_cells, 2), 256, 0, s>>>(n_cells, cp, m.urp, m.uci, m.A,
                                                              m.lrp, m.lci, m.lidx, doff, D, b,
                                                              xin, xout, omega, rev ? 1 : 0);
+}
+
+bool cc_supported(int np, int npc) { return (np == 20 || np == 35) && npc == 4; }
+
+template <typename T>
+void launch_jacobi_cc(hipStream_t s, int n_cells, int np, int npc, const int* cp, const int* rp,
+                      const int* ci, const T* AP, const int64_t* doff, const T* D, const T* r1,
+                      const T* x1, const T* e, T* xout, T omega, bool rev) {
+    const dim3 g(nblk(n_cells, 4)), blk(256);
+    const int r = rev ? 1 : 0;
+    if (np == 20 && npc == 4)
+        k_jacobi_cc<T, 20, 4><<<g, blk, 0, s>>>(n_cells, cp, rp, ci, AP, doff, D, r1, x1, e, xout,
+                                                omega, r);
+    else if (np == 35 && npc == 4)
+        k_jacobi_cc<T, 35, 4><<<g, blk, 0, s>>>(n_cells, cp, rp, ci, AP, doff, D, r1, x1, e, xout,
+                                                omega, r);
 }
 
 template <typename T>
@@ -1060,7 +1197,7 @@ void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const 
 
 #define XDG_INST(T)                                                                           \
     template void launch_spmv<T>(hipStream_t, int, int, int, const int*, const int*, const T*, \
-                                 const T*, const T*, T*, int, bool);                           \
+                                 const T*, const T*, T*, int, bool, T*);                       \
     template void launch_jacobi<T>(hipStream_t, bool, int, int, const int*, const int*,        \
                                    const int*, const T*, const int64_t*, const T*, const T*,   \
                                    const T*, T*, T, bool);                                     \
@@ -1072,7 +1209,10 @@ void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const 
     template void launch_prolong_dense<T>(hipStream_t, int, int, int, const int*, const int*,  \
                                           const T*, const T*, T*);                     \
     template void launch_spmv_sym<T>(hipStream_t, int, int, const SymRows<T>&, const T*,       \
-                                     const T*, T*, int, bool);                                 \
+                                     const T*, T*, int, bool, T*);                             \
+    template void launch_jacobi_cc<T>(hipStream_t, int, int, int, const int*, const int*,      \
+                                      const int*, const T*, const int64_t*, const T*,          \
+                                      const T*, const T*, const T*, T*, T, bool);              \
     template void launch_jacobi_sym<T>(hipStream_t, int, const int*, const SymRows<T>&,        \
                                        const int64_t*, const T*, const T*, const T*, T*, T,    \
                                        bool);

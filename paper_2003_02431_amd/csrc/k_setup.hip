@@ -78,6 +78,18 @@ __global__ void k_extract_leading(int64_t nnzb, int npf, int npc, const double* 
     Ac[t] = A[b * npf * npf + (int64_t)c * npf + r];
 }
 
+// AP[b] = the leading npc columns of block b (column-major: its first
+// np*npc entries)
+template <typename Tout>
+__global__ void k_leading_columns(int64_t nnzb, int np, int npc, const double* __restrict__ A,
+                                  Tout* __restrict__ AP) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = np * npc;
+    if (t >= nnzb * w) return;
+    const int64_t b = t / w;
+    AP[t] = (Tout)A[b * np * np + (t - b * w)];
+}
+
 // out[k] = in[idx[k]] block by block (the upper blocks of a symmetric level)
 template <typename Tin, typename Tout>
 __global__ void k_gather_blocks(int64_t n, int bs, const int* __restrict__ idx,
@@ -416,45 +428,117 @@ __global__ __launch_bounds__(256) void k_cgj_row(int nt, int K, int ld, double* 
     }
 }
 
-// A_IJ <- A_IJ - A_IK A_KJ for I, J != K (row K already updated).  When a
-// next panel exists, the group that updates its pivot tile A_{K+1,K+1} is
-// dispatched first and also inverts that tile into Pn (the next panel's P),
-// so the pivot inversion overlaps the rest of the update.
+// ---- 32 x 32 tile products on the FP64 matrix cores ------------------------
+// v_mfma_f64_16x16x4f64, lane layout (checked on gfx950): A operand (16 x 4)
+// lane l holds A[l % 16][l / 16]; B operand (4 x 16) lane l holds
+// B[l / 16][l % 16]; result (16 x 16) lane l, register r holds
+// D[l / 16 + 4 r][l % 16].  A 32 x 32 tile is 2 x 2 such blocks; one wave
+// multiplies two tiles in 8 k-steps of 4.  Row kk of the B operand of a
+// product lives in the same lane and register (r = kk % 4 of block row
+// kk / 4) as the result of the previous product, so chained products need
+// no data movement.
+typedef double cgj_f64x4 __attribute__((ext_vector_type(4)));
+
+struct TileAcc {
+    cgj_f64x4 d[2][2];
+};
+
+// D element (i, j) of the tile held by `lane`, register r of block (mi, nj)
+__device__ __forceinline__ int tile_d_row(int lane, int mi, int r) { return 16 * mi + (lane >> 4) + 4 * r; }
+__device__ __forceinline__ int tile_d_col(int lane, int nj) { return 16 * nj + (lane & 15); }
+
+// acc (+)= sgn * X Y with X, Y 32 x 32 row-major at leading dimensions ldx, ldy
+__device__ __forceinline__ void tile_mma(const double* __restrict__ X, int ldx,
+                                         const double* __restrict__ Y, int ldy, double sgn,
+                                         int lane, TileAcc& acc) {
+    const int li = lane & 15, lk = lane >> 4;
+    double a[8][2], b[8][2];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            a[kk][m] = sgn * X[(int64_t)(16 * m + li) * ldx + 4 * kk + lk];
+            b[kk][m] = Y[(int64_t)(4 * kk + lk) * ldy + 16 * m + li];
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj)
+                acc.d[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk][mi], b[kk][nj],
+                                                                     acc.d[mi][nj], 0, 0, 0);
+}
+
+__device__ __forceinline__ void tile_load(const double* __restrict__ T, int ld, int lane,
+                                          TileAcc& acc) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc.d[mi][nj][r] = T[(int64_t)tile_d_row(lane, mi, r) * ld + tile_d_col(lane, nj)];
+}
+
+__device__ __forceinline__ void tile_store(double* __restrict__ T, int ld, int lane,
+                                           const TileAcc& acc, double sgn) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                T[(int64_t)tile_d_row(lane, mi, r) * ld + tile_d_col(lane, nj)] =
+                    sgn * acc.d[mi][nj][r];
+}
+
+__device__ __forceinline__ void tile_zero(TileAcc& acc) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) acc.d[mi][nj] = cgj_f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// A_IJ <- A_IJ - A_IK A_KJ for I, J != K (row K already updated).  One wave
+// per tile, four tiles (2 x 2 of the tile grid without row and column K) per
+// group.  When a next panel exists, the group holding the pivot tile
+// A_{K+1,K+1} is dispatched first and, after its update, inverts that tile
+// into Pn (the next panel's P), so the pivot inversion overlaps the rest of
+// the update.
 __global__ __launch_bounds__(256) void k_cgj_update(int nt, int K, int ld, double* __restrict__ A,
                                                     double* __restrict__ Pn, int* err) {
-    __shared__ double u[NB][NB + 1], v[NB][NB + 1];
     __shared__ double a[NB * NB];
-    const int m = nt - 1;
-    int t = blockIdx.x;
+    const int m = nt - 1;                  // tiles per dimension without K
+    const int G = (m + 1) / 2;             // groups per dimension
     const bool next = K + 1 < nt;
-    if (next) {
-        const int tn = K * m + K;          // reduced index of (K+1, K+1)
-        t = t == 0 ? tn : (t == tn ? 0 : t);
-    }
-    const int Ip = t / m, Jp = t - Ip * m;
-    const int I = Ip + (Ip >= K ? 1 : 0), J = Jp + (Jp >= K ? 1 : 0);
-    load_tile(u, A, ld, I, K);
-    load_tile(v, A, ld, K, J);
-    __syncthreads();
-    // thread t: column c = t % 32, rows 4 (t / 32) .. +3 (each v[k][c] read once)
-    const int c = threadIdx.x % NB, r0 = 4 * (threadIdx.x / NB);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < NB; ++k) {
-        const double vk = v[k][c];
+    int g = blockIdx.x;
+    const int gs = (K / 2) * G + K / 2;    // group of reduced tile (K, K) = tile (K+1, K+1)
+    if (next) g = g == 0 ? gs : (g == gs ? 0 : g);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int Ip = 2 * (g / G) + (w >> 1), Jp = 2 * (g % G) + (w & 1);
+    const bool pivot_group = next && g == gs;
+    if (Ip < m && Jp < m) {
+        const int I = Ip + (Ip >= K ? 1 : 0), J = Jp + (Jp >= K ? 1 : 0);
+        double* Cij = A + (int64_t)(I * NB) * ld + J * NB;
+        TileAcc acc;
+        tile_load(Cij, ld, lane, acc);
+        tile_mma(A + (int64_t)(I * NB) * ld + K * NB, ld, A + (int64_t)(K * NB) * ld + J * NB, ld,
+                 -1.0, lane, acc);
+        tile_store(Cij, ld, lane, acc, 1.0);
+        if (pivot_group && I == K + 1 && J == K + 1) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] += u[r0 + q][k] * vk;
-    }
-    double nv[4];
+            for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        double* dst = &A[(int64_t)(I * NB + r0 + q) * ld + J * NB + c];
-        nv[q] = *dst - s[q];
-        *dst = nv[q];
-    }
-    if (next && I == K + 1 && J == K + 1) {      // uniform over the group
+                for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[c * NB + r0 + q] = nv[q];   // column-major
-        gj_lds_fixed<NB>(a, err);
+                    for (int r = 0; r < 4; ++r)          // column-major in LDS
+                        a[tile_d_col(lane, nj) * NB + tile_d_row(lane, mi, r)] = acc.d[mi][nj][r];
+        }
+    }
+    if (pivot_group) {                     // uniform over the group
+        gj_lds_fixed<NB>(a, err);          // starts with a barrier
         for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
             const int r = e / NB, cc = e - r * NB;
             Pn[e] = a[cc * NB + r];                                // row-major out
@@ -484,61 +568,59 @@ __global__ __launch_bounds__(256) void k_cgj_col(int nt, int K, int ld, double* 
 }
 
 // column K (with P = inverse of panel K's pivot) and row K+1 (with Pn, the
-// next pivot inverse) in one launch: groups 0..nt-1 do column K except tile
-// (K+1, K); groups nt.. do row K+1, and the group of tile (K+1, K) first
+// next pivot inverse) in one launch, one wave per tile: waves 0..nt-1 do
+// column K (A_IK <- -A_IK P; A_KK <- P) except tile (K+1, K); waves nt.. do
+// row K+1 (A_{K+1,J} <- Pn A_{K+1,J}), and the wave of tile (K+1, K) first
 // applies the column-K step to it, then the row-(K+1) step -- the order of
 // separate launches.  The two steps touch no other common tile.
-__global__ __launch_bounds__(256) void k_cgj_colrow(int nt, int K, int ld, double* __restrict__ A,
-                                                    const double* __restrict__ P,
-                                                    const double* __restrict__ Pn) {
-    __shared__ double p[NB][NB + 1], t[NB][NB + 1];
+__global__ __launch_bounds__(64) void k_cgj_colrow(int nt, int K, int ld, double* __restrict__ A,
+                                                   const double* __restrict__ P,
+                                                   const double* __restrict__ Pn) {
     const int w = blockIdx.x;
+    const int lane = threadIdx.x;
+    TileAcc acc;
+    tile_zero(acc);
     if (w < nt) {                              // column K
         const int I = w;
         if (I == K + 1) return;
-        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = P[e];
+        double* T = A + (int64_t)(I * NB) * ld + K * NB;
         if (I == K) {
-            for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
-                A[(int64_t)(K * NB + e / NB) * ld + K * NB + e % NB] = P[e];
+            for (int e = lane; e < NB * NB; e += 64) T[(int64_t)(e / NB) * ld + e % NB] = P[e];
             return;
         }
-        load_tile(t, A, ld, I, K);
-        __syncthreads();
-        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-            const int r = e / NB, c = e - r * NB;
-            double sum = 0.0;
-            for (int k = 0; k < NB; ++k) sum += t[r][k] * p[k][c];
-            A[(int64_t)(I * NB + r) * ld + K * NB + c] = -sum;
-        }
+        tile_mma(T, ld, P, NB, 1.0, lane, acc);
+        tile_store(T, ld, lane, acc, -1.0);
         return;
     }
     const int jj = w - nt;                     // row K+1, J != K+1
     const int J = jj + (jj >= K + 1 ? 1 : 0);
-    load_tile(t, A, ld, K + 1, J);
-    if (J == K) {                              // column-K step on tile (K+1, K) first
-        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = P[e];
-        __syncthreads();
-        double v[4];
-        int q = 0;
-        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x, ++q) {
-            const int r = e / NB, c = e - r * NB;
-            double sum = 0.0;
-            for (int k = 0; k < NB; ++k) sum += t[r][k] * p[k][c];
-            v[q] = -sum;
-        }
-        __syncthreads();
-        q = 0;
-        for (int e = threadIdx.x; e < NB * NB; e += blockDim.x, ++q) t[e / NB][e % NB] = v[q];
+    double* T = A + (int64_t)((K + 1) * NB) * ld + J * NB;
+    if (J == K) {
+        // t = -A_{K+1,K} P, then A_{K+1,K} <- Pn t; t stays in registers as
+        // the B operand of the second product
+        tile_mma(T, ld, P, NB, -1.0, lane, acc);
+        const int li = lane & 15;
+        double a[8][2];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+                a[kk][mi] = Pn[(16 * mi + li) * NB + 4 * kk + (lane >> 4)];
+        TileAcc out;
+        tile_zero(out);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < 2; ++nj)
+                    out.d[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        a[kk][mi], acc.d[kk / 4][nj][kk % 4], out.d[mi][nj], 0, 0, 0);
+        tile_store(T, ld, lane, out, 1.0);
+        return;
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) p[e / NB][e % NB] = Pn[e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-        const int r = e / NB, c = e - r * NB;
-        double sum = 0.0;
-        for (int k = 0; k < NB; ++k) sum += p[r][k] * t[k][c];
-        A[(int64_t)((K + 1) * NB + r) * ld + J * NB + c] = sum;
-    }
+    tile_mma(Pn, NB, T, ld, 1.0, lane, acc);
+    tile_store(T, ld, lane, acc, 1.0);
 }
 
 template <typename Tin, typename Tout>
@@ -554,6 +636,16 @@ void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* 
     const size_t lds = (size_t)bpg * np * np * sizeof(double);
     k_transpose_blocks<T><<<nblk(nnzb, bpg), 256, lds, s>>>(nnzb, np, bpg, in, out);
 }
+template <typename Tout>
+void launch_leading_columns(hipStream_t s, int64_t nnzb, int np, int npc, const double* A,
+                            Tout* AP) {
+    if (nnzb > 0)
+        k_leading_columns<Tout><<<nblk(nnzb * np * npc, 256), 256, 0, s>>>(nnzb, np, npc, A, AP);
+}
+template void launch_leading_columns<double>(hipStream_t, int64_t, int, int, const double*,
+                                             double*);
+template void launch_leading_columns<float>(hipStream_t, int64_t, int, int, const double*,
+                                            float*);
 template <typename Tin, typename Tout>
 void launch_gather_blocks(hipStream_t s, int64_t n, int bs, const int* idx, const Tin* in,
                           Tout* out) {
@@ -623,9 +715,12 @@ void launch_coarse_gj_step(hipStream_t s, int nt, int K, int ld, double* A, doub
         k_cgj_pivot<<<1, 256, 0, s>>>(K, ld, A, P, err);
         if (nt > 1) k_cgj_row<<<nt - 1, 256, 0, s>>>(nt, K, ld, A, P);
     }
-    if (nt > 1) k_cgj_update<<<(nt - 1) * (nt - 1), 256, 0, s>>>(nt, K, ld, A, Pn, err);
+    if (nt > 1) {
+        const int G = nt / 2;              // ceil((nt - 1) / 2) groups of 2 x 2 tiles per dimension
+        k_cgj_update<<<G * G, 256, 0, s>>>(nt, K, ld, A, Pn, err);
+    }
     if (K + 1 < nt)
-        k_cgj_colrow<<<2 * nt - 1, 256, 0, s>>>(nt, K, ld, A, P, Pn);
+        k_cgj_colrow<<<2 * nt - 1, 64, 0, s>>>(nt, K, ld, A, P, Pn);
     else
         k_cgj_col<<<nt, 256, 0, s>>>(nt, K, ld, A, P);
 }

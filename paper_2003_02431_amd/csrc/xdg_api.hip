@@ -188,14 +188,13 @@ static int invert_coarsest(xdg_handle* h, Level& lv) {
     return XDG_OK;
 }
 
-// Numeric phase of the set-up from level-0 values `raw` (device, row-major
-// blocks): layout change, Galerkin chain, cell-block and coarsest inverses,
-// FP32 copies.  Errors of the inversions are reported through d_err.
-// the symmetric level's upper blocks from its full FP64 blocks
+// the level's derived FP64 copies from its full FP64 blocks: the symmetric
+// level's upper blocks and the leading columns (FP32 ones: convert_level32)
 static void sym_refresh(xdg_handle* h, Level& lv) {
     if (lv.sym)
         launch_gather_blocks<double, double>(h->s, lv.nnzb_u, lv.np * lv.np, lv.ufull, lv.A64,
                                              lv.As64);
+    if (lv.AP64) launch_leading_columns<double>(h->s, lv.nnzb, lv.np, lv.npc, lv.A64, lv.AP64);
 }
 
 // FP32 copies of a level's operator and cell inverses (mixed precision)
@@ -205,9 +204,13 @@ static void convert_level32(xdg_handle* h, Level& lv) {
                                             lv.As32);
     else
         launch_convert<double, float>(h->s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
+    if (lv.AP32) launch_leading_columns<float>(h->s, lv.nnzb, lv.np, lv.npc, lv.A64, lv.AP32);
     launch_convert<double, float>(h->s, lv.dsize, lv.D64, lv.D32);
 }
 
+// Numeric phase of the set-up from level-0 values `raw` (device, row-major
+// blocks): layout change, Galerkin chain, cell-block and coarsest inverses,
+// FP32 copies.  Errors of the inversions are reported through d_err.
 static int numeric_setup(xdg_handle* h, const double* raw) {
     hipStream_t s = h->s;
     const int nl = (int)h->L.size();
@@ -249,19 +252,19 @@ static int check_setup_error(xdg_handle* h) {
 // Level operators on the level's storage
 
 template <typename T>
-void xdg::level_spmv(xdg_handle* h, Level& lv, int mode, const T* x, const T* b, T* y,
-                     int npc) {
+void xdg::level_spmv(xdg_handle* h, Level& lv, int mode, const T* x, const T* b, T* y, int npc,
+                     T* yfull) {
     const bool rev = lv.next_dir();
     if (lv.sym)
-        launch_spmv_sym<T>(h->s, mode, lv.n_rows, P<T>::sym(lv), x, b, y, npc, rev);
+        launch_spmv_sym<T>(h->s, mode, lv.n_rows, P<T>::sym(lv), x, b, y, npc, rev, yfull);
     else
         launch_spmv<T>(h->s, mode, lv.n_rows, lv.np, lv.rp, lv.ci, P<T>::A(lv), x, b, y, npc,
-                       rev);
+                       rev, yfull);
 }
 template void xdg::level_spmv<double>(xdg_handle*, Level&, int, const double*, const double*,
-                                      double*, int);
+                                      double*, int, double*);
 template void xdg::level_spmv<float>(xdg_handle*, Level&, int, const float*, const float*,
-                                     float*, int);
+                                     float*, int, float*);
 
 void xdg::level_spmv_dot(xdg_handle* h, Level& lv, const double* x, double* y, double* out) {
     const bool rev = lv.next_dir();
@@ -374,14 +377,31 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
     } else {
         smooth_from_zero<T>(h, f, h->opt.nu_pre);
     }
+    // first post sweep from the kept residual and the coarse correction
+    // (M P from the leading columns), where the level stores them
+    const bool cc = f.t_kind == XDG_T_PTRUNC && P<T>::AP(f) && h->opt.nu_post >= 1;
     if (f.t_kind == XDG_T_PTRUNC) {
-        xdg::level_spmv<T>(h, f, SPMV_RESID_TRUNC, P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np);
+        xdg::level_spmv<T>(h, f, SPMV_RESID_TRUNC, P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np,
+                           cc ? P<T>::r(f) : nullptr);
     } else {
         xdg::level_spmv<T>(h, f, SPMV_RESID, P<T>::x(f), P<T>::b(f), P<T>::r(f), 0);
         launch_restrict_dense<T>(h->s, c.n_rows, f.n_rows, f.np, c.np, f.chp, f.chi, f.ridx,
                                  P<T>::R(f), P<T>::r(f), P<T>::b(c), P<T>::y(f));
     }
     vcycle<T>(h, l + 1);
+    if (cc) {
+        T*& x = P<T>::x(f);
+        T*& y = P<T>::y(f);
+        const bool last = h->opt.nu_post == 1;
+        T* dst = last && out ? out : y;
+        launch_jacobi_cc<T>(h->s, f.n_cells, f.np, c.np, f.cp, f.rp, f.ci, P<T>::AP(f), f.doff,
+                            P<T>::D(f), P<T>::r(f), x, P<T>::x(c), dst, (T)h->opt.omega,
+                            f.next_dir());
+        if (last && out) return;
+        std::swap(x, y);
+        smooth_more<T>(h, f, h->opt.nu_post - 1, out);
+        return;
+    }
     if (f.t_kind == XDG_T_PTRUNC)
         launch_prolong_trunc<T>(h->s, f.n_rows, f.np, c.np, P<T>::x(c), P<T>::x(f));
     else
@@ -451,7 +471,8 @@ constexpr int kMaxCycleLevels = 32;
 
 // Lays the V-cycle's work vectors out in 256-byte aligned pieces from base
 // (base = nullptr: only counts) and returns the doubles used.  Every level
-// holds b, x, y and, above a dense transfer, r in the cycle's precision; the
+// holds b, x, y and, above a dense transfer or where the first post sweep
+// uses the kept residual, r in the cycle's precision; the
 // coarsest level holds b, x (and b64, x64 for the FP32 cycle's FP64 solve).
 int64_t carve_cycle(const xdg_handle* h, double* base, CyclePtrs* out) {
     int64_t used = 0;
@@ -470,7 +491,8 @@ int64_t carve_cycle(const xdg_handle* h, double* base, CyclePtrs* out) {
             c.b32 = reinterpret_cast<float*>(take(n, 4));
             c.x32 = reinterpret_cast<float*>(take(n, 4));
             if (!last) c.y32 = reinterpret_cast<float*>(take(n, 4));
-            if (!last && lv.t_kind == XDG_T_DENSE) c.r32 = reinterpret_cast<float*>(take(n, 4));
+            if (!last && (lv.t_kind == XDG_T_DENSE || lv.AP32))
+                c.r32 = reinterpret_cast<float*>(take(n, 4));
             if (last) {
                 c.b64 = reinterpret_cast<double*>(take(n, 8));
                 c.x64 = reinterpret_cast<double*>(take(n, 8));
@@ -479,7 +501,8 @@ int64_t carve_cycle(const xdg_handle* h, double* base, CyclePtrs* out) {
             c.b64 = reinterpret_cast<double*>(take(n, 8));
             c.x64 = reinterpret_cast<double*>(take(n, 8));
             if (!last) c.y64 = reinterpret_cast<double*>(take(n, 8));
-            if (!last && lv.t_kind == XDG_T_DENSE) c.r64 = reinterpret_cast<double*>(take(n, 8));
+            if (!last && (lv.t_kind == XDG_T_DENSE || lv.AP64))
+                c.r64 = reinterpret_cast<double*>(take(n, 8));
         }
         if (out) out[l] = c;
     }
@@ -742,6 +765,13 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     for (int l = 0; l + 1 < n_levels; ++l) {
         Level& lv = h->L[l];
         CHK(h->alloc(&lv.D64, lv.dsize));
+        // leading columns for the post sweep after a p-coarse correction: the
+        // single-column cycle at level 0
+        if (l == 0 && h->nrhs == 1 && lv.t_kind == XDG_T_PTRUNC && cc_supported(lv.np, lv.npc)) {
+            const size_t nap = (size_t)lv.nnzb * lv.np * lv.npc;
+            if (h->mixed) CHK(h->alloc(&lv.AP32, nap));
+            else CHK(h->alloc(&lv.AP64, nap));
+        }
         if (h->mixed) {
             if (!lv.sym) CHK(h->alloc(&lv.A32, (size_t)lv.nnzb * lv.np * lv.np));
             CHK(h->alloc(&lv.D32, lv.dsize));

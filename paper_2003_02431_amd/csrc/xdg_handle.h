@@ -84,6 +84,11 @@ struct Level {
     int* ufull = nullptr;
     double* As64 = nullptr;
     float* As32 = nullptr;
+    // leading npc columns of every block (np x npc column-major, the level's
+    // pattern) for the first post sweep after a p-coarse correction
+    // (levels with a p-truncation below them and a kernel for the sizes)
+    double* AP64 = nullptr;
+    float* AP32 = nullptr;
     // direction of the next streaming pass over this level's blocks
     // (alternates; reset at every public call so that results are repeatable)
     bool rev_next = false;
@@ -104,6 +109,7 @@ template <> struct P<double> {
     static double*& x(Level& l) { return l.x64; }
     static double*& y(Level& l) { return l.y64; }
     static double*& r(Level& l) { return l.r64; }
+    static double* AP(Level& l) { return l.AP64; }
     static SymRows<double> sym(Level& l) {
         SymRows<double> m;
         m.urp = l.urp; m.uci = l.uci; m.lrp = l.lrp; m.lci = l.lci; m.lidx = l.lidx;
@@ -119,6 +125,7 @@ template <> struct P<float> {
     static float*& x(Level& l) { return l.x32; }
     static float*& y(Level& l) { return l.y32; }
     static float*& r(Level& l) { return l.r32; }
+    static float* AP(Level& l) { return l.AP32; }
     static SymRows<float> sym(Level& l) {
         SymRows<float> m;
         m.urp = l.urp; m.uci = l.uci; m.lrp = l.lrp; m.lci = l.lci; m.lidx = l.lidx;
@@ -224,8 +231,10 @@ int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap,
 namespace xdg {
 // the level's operator on its storage (all blocks, or the symmetric upper
 // blocks); every call flips the level's streaming direction
+// (SPMV_RESID_TRUNC: yfull != nullptr also keeps the whole residual)
 template <typename T>
-void level_spmv(xdg_handle* h, Level& lv, int mode, const T* x, const T* b, T* y, int npc);
+void level_spmv(xdg_handle* h, Level& lv, int mode, const T* x, const T* b, T* y, int npc,
+                T* yfull = nullptr);
 // y = M x and *out = x . y on level 0 (fused where the block size allows)
 void level_spmv_dot(xdg_handle* h, Level& lv, const double* x, double* y, double* out);
 // one damped block-Jacobi sweep (first: x_in = 0, the matrix is not read)

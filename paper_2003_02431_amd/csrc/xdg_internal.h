@@ -29,9 +29,11 @@ enum SpmvMode { SPMV_AX = 0, SPMV_RESID = 1, SPMV_RESID_TRUNC = 2, SPMV_AX_DOT =
 // (Infinity) cache.  Results do not depend on it (rows and cells are
 // independent), except the per-workgroup partials of launch_spmv_dot, which
 // are added in launch order.
+// yfull (SPMV_RESID_TRUNC, Np = 20 or 35): also keep the whole residual there
 template <typename T>
 void launch_spmv(hipStream_t s, int mode, int n_rows, int np, const int* rp, const int* ci,
-                 const T* A, const T* x, const T* b, T* y, int npc, bool rev = false);
+                 const T* A, const T* x, const T* b, T* y, int npc, bool rev = false,
+                 T* yfull = nullptr);
 template <typename T>
 void launch_jacobi(hipStream_t s, bool first, int n_cells, int np, const int* cell_ptr,
                    const int* rp, const int* ci, const T* A, const int64_t* doff, const T* D,
@@ -72,7 +74,7 @@ struct SymRows {
 };
 template <typename T>
 void launch_spmv_sym(hipStream_t s, int mode, int n_rows, const SymRows<T>& m, const T* x,
-                     const T* b, T* y, int npc, bool rev);
+                     const T* b, T* y, int npc, bool rev, T* yfull = nullptr);
 void launch_spmv_dot_sym(hipStream_t s, int n_rows, const SymRows<double>& m, const double* x,
                          double* y, double* partial, double* out, bool rev);
 // x_in given (not the first sweep from zero)
@@ -80,6 +82,19 @@ template <typename T>
 void launch_jacobi_sym(hipStream_t s, int n_cells, const int* cp, const SymRows<T>& m,
                        const int64_t* doff, const T* D, const T* b, const T* xin, T* xout,
                        T omega, bool rev);
+// First post sweep after a p-coarse correction e (npc leading modes per row):
+// x_out = x1 + P e + omega D^-1 (r1 - (M P) e), r1 = b - M x1 kept by the
+// residual pass, AP the leading npc columns of every block (np x npc
+// column-major, the level's pattern).  cc_supported: block sizes with the kernel.
+bool cc_supported(int np, int npc);
+template <typename T>
+void launch_jacobi_cc(hipStream_t s, int n_cells, int np, int npc, const int* cp, const int* rp,
+                      const int* ci, const T* AP, const int64_t* doff, const T* D, const T* r1,
+                      const T* x1, const T* e, T* xout, T omega, bool rev);
+// AP[b] = the first np*npc entries of block b (its leading npc columns)
+template <typename Tout>
+void launch_leading_columns(hipStream_t s, int64_t nnzb, int np, int npc, const double* A,
+                            Tout* AP);
 // out[k] = in[idx[k]] for blocks of bs entries (converted to Tout)
 template <typename Tin, typename Tout>
 void launch_gather_blocks(hipStream_t s, int64_t n, int bs, const int* idx, const Tin* in,
