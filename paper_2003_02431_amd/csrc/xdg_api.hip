@@ -168,11 +168,11 @@ static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* p
     return XDG_OK;
 }
 
-static int invert_cells(xdg_handle* h, Level& lv) {
-    HIPCHK(hipMemsetAsync(lv.D64, 0, lv.dsize * sizeof(double), h->s));
-    launch_gather_cells(h->s, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff, lv.D64,
+static int invert_cells(xdg_handle* h, Level& lv, hipStream_t s) {
+    HIPCHK(hipMemsetAsync(lv.D64, 0, lv.dsize * sizeof(double), s));
+    launch_gather_cells(s, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff, lv.D64,
                         nullptr);
-    launch_gj_batched(h->s, lv.n_cells, lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64, h->d_err,
+    launch_gj_batched(s, lv.n_cells, lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64, h->d_err,
                       nullptr);
     HIPCHK(hipGetLastError());
     return XDG_OK;
@@ -198,14 +198,14 @@ static void sym_refresh(xdg_handle* h, Level& lv) {
 }
 
 // FP32 copies of a level's operator and cell inverses (mixed precision)
-static void convert_level32(xdg_handle* h, Level& lv) {
+static void convert_level32(Level& lv, hipStream_t s) {
     if (lv.sym)
-        launch_gather_blocks<double, float>(h->s, lv.nnzb_u, lv.np * lv.np, lv.ufull, lv.A64,
+        launch_gather_blocks<double, float>(s, lv.nnzb_u, lv.np * lv.np, lv.ufull, lv.A64,
                                             lv.As32);
     else
-        launch_convert<double, float>(h->s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
-    if (lv.AP32) launch_leading_columns<float>(h->s, lv.nnzb, lv.np, lv.npc, lv.A64, lv.AP32);
-    launch_convert<double, float>(h->s, lv.dsize, lv.D64, lv.D32);
+        launch_convert<double, float>(s, (int64_t)lv.nnzb * lv.np * lv.np, lv.A64, lv.A32);
+    if (lv.AP32) launch_leading_columns<float>(s, lv.nnzb, lv.np, lv.npc, lv.A64, lv.AP32);
+    launch_convert<double, float>(s, lv.dsize, lv.D64, lv.D32);
 }
 
 // Numeric phase of the set-up from level-0 values `raw` (device, row-major
@@ -230,10 +230,17 @@ static int numeric_setup(xdg_handle* h, const double* raw) {
             launch_galerkin_dense(s, c.nnzb, f.np, c.np, f.g_ptr, f.g_fb, f.g_row, f.g_col,
                                   f.A64, f.R64, c.A64, nullptr);
     }
-    for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l]));
-    CHK(invert_coarsest(h, h->L[nl - 1]));
+    // the cell-block inversions and FP32 copies of every level on the side
+    // stream while the coarsest inverse (a chain of small launches) runs on
+    // the handle's stream; joined before anything reads them
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
+    for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l], h->s2));
     if (h->mixed)
-        for (int l = 0; l + 1 < nl; ++l) convert_level32(h, h->L[l]);
+        for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], h->s2);
+    HIPCHK(hipEventRecord(h->ev_join, h->s2));
+    CHK(invert_coarsest(h, h->L[nl - 1]));
+    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
     if (h->nrhs == kNrhs) CHK(mrhs_numeric(h));
     HIPCHK(hipGetLastError());
     return XDG_OK;
@@ -553,6 +560,12 @@ extern "C" const char* xdg_last_error(void) { return xdg::last_error_text().c_st
 extern "C" void xdg_destroy(xdg_handle* h) {
     if (!h) return;
     if (h->s) (void)hipStreamSynchronize(h->s);
+    if (h->s2) {
+        (void)hipStreamSynchronize(h->s2);
+        (void)hipStreamDestroy(h->s2);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     if (h->h_stage) (void)hipHostFree(h->h_stage);
@@ -672,6 +685,10 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // side stream of the set-up (default priority) and its fork / join events
+    HIPCHK(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     CHK(h->alloc(&h->d_err, 1));
 
     // -- symbolic phase: patterns, transfers, allocations ----------------------
@@ -1386,7 +1403,7 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
     }
     CHK(invert_coarsest(h, h->L[nl - 1]));
     if (h->mixed)
-        for (int l = 0; l + 1 < nl; ++l) convert_level32(h, h->L[l]);
+        for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], s);
     HIPCHK(hipGetLastError());
     return check_setup_error(h);   // synchronises: the stage may be reused afterwards
 }

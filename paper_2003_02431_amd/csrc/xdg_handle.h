@@ -141,6 +141,8 @@ using xdg::P;
 
 struct xdg_handle {
     hipStream_t s = nullptr;
+    hipStream_t s2 = nullptr;       // side stream of the numeric set-up
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int dev = 0;                    // device current at xdg_create
     xdg_options opt{};
     std::vector<Level> L;
