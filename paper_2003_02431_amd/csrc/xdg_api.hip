@@ -1393,17 +1393,25 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
                 launch_galerkin_dense(s, (int)bcnt[t], f.np, lv.np, f.g_ptr, f.g_fb, f.g_row,
                                       f.g_col, f.A64, f.R64, lv.A64, bl);
         }
-        if (t + 1 < nl && ccnt[t] > 0) {
-            const int* cl = h->d_stage + coff[t];
-            launch_gather_cells(s, (int)ccnt[t], lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff,
-                                lv.D64, cl);
-            launch_gj_batched(s, (int)ccnt[t], lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64, h->d_err,
-                              cl);
-        }
     }
-    CHK(invert_coarsest(h, h->L[nl - 1]));
+    // the listed cells' inversions and the FP32 copies on the side stream while
+    // the coarsest inverse is rebuilt, as in the full set-up
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
+    for (int t = 0; t + 1 < nl; ++t) {
+        if (ccnt[t] == 0) continue;
+        Level& lv = h->L[t];
+        const int* cl = h->d_stage + coff[t];
+        launch_gather_cells(h->s2, (int)ccnt[t], lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff,
+                            lv.D64, cl);
+        launch_gj_batched(h->s2, (int)ccnt[t], lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64,
+                          h->d_err, cl);
+    }
     if (h->mixed)
-        for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], s);
+        for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], h->s2);
+    HIPCHK(hipEventRecord(h->ev_join, h->s2));
+    CHK(invert_coarsest(h, h->L[nl - 1]));
+    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
     HIPCHK(hipGetLastError());
     return check_setup_error(h);   // synchronises: the stage may be reused afterwards
 }
