@@ -124,7 +124,18 @@ __global__ __launch_bounds__(1024) void k_dot_final_wide(const double* __restric
                                                          int np, double* __restrict__ out) {
     __shared__ double sh[16];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
+    // the thread's strided partials in order; eight loads in flight at a time
+    constexpr int U = 8;
+    const int stride = (int)blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * stride < np; i += U * stride) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = partial[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u];
+    }
+    for (; i < np; i += stride) acc += partial[i];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) sh[w] = acc;

@@ -842,6 +842,106 @@ __global__ __launch_bounds__(256) void k_jacobi_g(int n_cells, const int* __rest
     }
 }
 
+// First post sweep after an aggregation coarse correction, the small-block
+// form of k_jacobi_cc: with x2 = x1 + R e (fine row i takes R_i e_parent(i))
+// and r1 = b - M x1 kept by the residual pass,
+//   b - M x2 = r1 - (M R) e,
+// where (M R)_iJ = sum over the row's blocks (i, j) with parent(j) = J of
+// M_ij R_j (np x npc, column-major, formed at set-up; the distinct coarse
+// neighbours of a row are fewer than its fine ones).  One 16-lane group per
+// cell, as k_jacobi_g; the prolongation is fused.
+template <typename T, int NP, int NC>
+__device__ __forceinline__ void row_stream_nc_g(int b0, int nb, const int* __restrict__ ci,
+                                                const T* __restrict__ AR,
+                                                const T* __restrict__ e, int lane,
+                                                T (&acc)[GrpCfg<T, NP>::VEC]) {
+    using R = GrpCfg<T, NP>;
+    constexpr int V = R::VEC;
+    const int gl = lane & (kGS - 1), gb = lane - gl;
+    const int q = gl % R::L, cl = gl / R::L;
+    const bool act = cl < R::C;
+    const int colreg = gl < nb ? ci[b0 + gl] : 0;
+    const T* Ar = AR + (int64_t)b0 * (NP * NC);
+    const int E = nb * (NP * NC);
+    const int off = cl * NP + q * V;
+    for (int base = 0; base < E; base += R::CH) {
+        const int ee = base + off;
+        const bool ok = act && ee < E;
+        const int xi = ee / NP;
+        const int bb = xi / NC;
+        int col = __shfl(colreg, gb + (bb & (kGS - 1)), 64);
+        if (ok) {
+            if (bb >= kGS) col = ci[b0 + bb];
+            const T ev = e[(int64_t)col * NC + (xi - bb * NC)];
+            T a[V];
+            load_vec<T, V>(Ar + ee, a);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] += a[v] * ev;
+        }
+    }
+}
+
+template <typename T, int NP, int NC>
+__global__ __launch_bounds__(256) void k_jacobi_cc_g(int n_cells, const int* __restrict__ cell_ptr,
+                                                     const int* __restrict__ arp,
+                                                     const int* __restrict__ arc,
+                                                     const T* __restrict__ AR,
+                                                     const int64_t* __restrict__ doff,
+                                                     const T* __restrict__ D,
+                                                     const T* __restrict__ r1,
+                                                     const T* __restrict__ x1,
+                                                     const T* __restrict__ e,
+                                                     const int* __restrict__ parent,
+                                                     const int* __restrict__ ridx,
+                                                     const T* __restrict__ Rt,
+                                                     T* __restrict__ xout, T omega) {
+    using R = GrpCfg<T, NP>;
+    constexpr int G = 256 / kGS;
+    __shared__ T res[G][kMaxCell];
+    const int lane = threadIdx.x & 63;
+    const int grp = threadIdx.x / kGS, gl = lane & (kGS - 1);
+    const int cell = (int)blockIdx.x * G + grp;
+    const bool valid = cell < n_cells;
+    int r0 = 0, r1c = 0;
+    if (valid) {
+        r0 = cell_ptr[cell];
+        r1c = cell_ptr[cell + 1];
+    }
+    const int nc = (r1c - r0) * NP;                // <= kMaxCell (checked on the host)
+    for (int row = r0; row < r1c; ++row) {
+        T acc[R::VEC];
+#pragma unroll
+        for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
+        const int beg = arp[row], nb = arp[row + 1] - beg;
+        row_stream_nc_g<T, NP, NC>(beg, nb, arc, AR, e, lane, acc);
+        reduce_groups_g<T, R::VEC>(acc, R::L, R::C, lane);
+        if (gl < R::L) {
+#pragma unroll
+            for (int v = 0; v < R::VEC; ++v) {
+                const int r = gl * R::VEC + v;
+                res[grp][(row - r0) * NP + r] = r1[(int64_t)row * NP + r] - acc[v];
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid) {
+        const T* Dc = D + doff[cell];
+        const int64_t base = (int64_t)r0 * NP;
+        for (int o = gl; o < nc; o += kGS) {
+            const int row = r0 + o / NP, a = o % NP;
+            const T* Ri = Rt + (int64_t)ridx[row] * NP * NC + a * NC;
+            const T* ep = e + (int64_t)parent[row] * NC;
+            T pe = 0;
+            for (int m = 0; m < NC; ++m) pe += Ri[m] * ep[m];
+            T acc = 0;
+            for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * res[grp][c];
+            xout[base + o] = (x1[base + o] + pe) + omega * acc;
+        }
+    }
+}
+
 template <typename T>
 __global__ void k_restrict_trunc(int n_rows, int npf, int npc, const T* __restrict__ rf,
                                  T* __restrict__ rc) {
@@ -1144,6 +1244,17 @@ void launch_jacobi_sym(hipStream_t s, int n_cells, const int* cp, const SymRows<
 }
 
 bool cc_supported(int np, int npc) { return (np == 20 || np == 35) && npc == 4; }
+bool cc_dense_supported(int np, int npc) { return np == 4 && npc == 4; }
+
+template <typename T>
+void launch_jacobi_cc_g(hipStream_t s, int n_cells, int np, int npc, const int* cp,
+                        const int* arp, const int* arc, const T* AR, const int64_t* doff,
+                        const T* D, const T* r1, const T* x1, const T* e, const int* parent,
+                        const int* ridx, const T* R, T* xout, T omega) {
+    if (np == 4 && npc == 4)
+        k_jacobi_cc_g<T, 4, 4><<<nblk(n_cells, 256 / kGS), 256, 0, s>>>(
+            n_cells, cp, arp, arc, AR, doff, D, r1, x1, e, parent, ridx, R, xout, omega);
+}
 
 template <typename T>
 void launch_jacobi_cc(hipStream_t s, int n_cells, int np, int npc, const int* cp, const int* rp,
@@ -1210,6 +1321,10 @@ void launch_coarse_gemv(hipStream_t s, int n, int ld, const double* Ainv, const 
                                           const T*, const T*, T*);                     \
     template void launch_spmv_sym<T>(hipStream_t, int, int, const SymRows<T>&, const T*,       \
                                      const T*, T*, int, bool, T*);                             \
+    template void launch_jacobi_cc_g<T>(hipStream_t, int, int, int, const int*, const int*,    \
+                                        const int*, const T*, const int64_t*, const T*,        \
+                                        const T*, const T*, const T*, const int*, const int*,  \
+                                        const T*, T*, T);                                      \
     template void launch_jacobi_cc<T>(hipStream_t, int, int, int, const int*, const int*,      \
                                       const int*, const T*, const int64_t*, const T*,          \
                                       const T*, const T*, const T*, T*, T, bool);              \

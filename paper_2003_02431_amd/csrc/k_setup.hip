@@ -78,6 +78,46 @@ __global__ void k_extract_leading(int64_t nnzb, int npf, int npc, const double* 
     Ac[t] = A[b * npf * npf + (int64_t)c * npf + r];
 }
 
+// (M R)_k for the blocks k = (i, J) of the aggregation-level product: sum over
+// the listed fine blocks b = (i, j), parent(j) = J, of M_b R_j (np x npc,
+// column-major out; M_b column-major, R_j row-major), in list order.  One
+// thread per entry.
+template <typename Tout>
+__global__ void k_ar_product(int64_t n_ar, int np, int npc, const int* __restrict__ lptr,
+                             const int* __restrict__ lb, const int* __restrict__ ci,
+                             const int* __restrict__ ridx, const double* __restrict__ A,
+                             const double* __restrict__ R, Tout* __restrict__ AR) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = np * npc;
+    if (t >= n_ar * w) return;
+    const int64_t k = t / w;
+    const int e = (int)(t - k * w);
+    const int c = e / np, r = e - c * np;
+    double acc = 0.0;
+    for (int q = lptr[k]; q < lptr[k + 1]; ++q) {
+        const int b = lb[q];
+        const double* Ab = A + (int64_t)b * np * np + r;
+        const double* Rj = R + (int64_t)ridx[ci[b]] * np * npc + c;
+        for (int kk = 0; kk < np; ++kk) acc += Ab[kk * np] * Rj[kk * npc];
+    }
+    AR[t] = (Tout)acc;
+}
+
+template <typename Tout>
+void launch_ar_product(hipStream_t s, int64_t n_ar, int np, int npc, const int* lptr,
+                       const int* lb, const int* ci, const int* ridx, const double* A,
+                       const double* R, Tout* AR) {
+    if (n_ar > 0)
+        k_ar_product<Tout><<<nblk(n_ar * np * npc, 256), 256, 0, s>>>(n_ar, np, npc, lptr, lb, ci,
+                                                                      ridx, A, R, AR);
+}
+template void launch_ar_product<double>(hipStream_t, int64_t, int, int, const int*, const int*,
+                                        const int*, const int*, const double*, const double*,
+                                        double*);
+template void launch_ar_product<float>(hipStream_t, int64_t, int, int, const int*, const int*,
+                                       const int*, const int*, const double*, const double*,
+                                       float*);
+
 // AP[b] = the leading npc columns of block b (column-major: its first
 // np*npc entries)
 template <typename Tout>

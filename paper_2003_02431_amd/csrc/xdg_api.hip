@@ -168,6 +168,52 @@ static int galerkin_symbolic(xdg_handle* h, Level& f, Level& c, const int32_t* p
     return XDG_OK;
 }
 
+// Pattern of (M R) for the post sweep after an aggregation coarse correction:
+// per fine row the distinct parents of its columns (ascending), and for every
+// such block the row's fine blocks that sum into it (ascending).
+static int ar_symbolic(xdg_handle* h, Level& f, const int32_t* parent) {
+    std::vector<int> arp(f.n_rows + 1, 0), arc, lptr(1, 0), lb;
+    std::vector<std::pair<int, int>> jb;
+    for (int i = 0; i < f.n_rows; ++i) {
+        jb.clear();
+        for (int b = f.h_rp[i]; b < f.h_rp[i + 1]; ++b) jb.push_back({parent[f.h_ci[b]], b});
+        std::stable_sort(jb.begin(), jb.end(),
+                         [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+                             return a.first < b.first;
+                         });
+        for (size_t q = 0; q < jb.size(); ++q) {
+            if (q == 0 || jb[q].first != jb[q - 1].first) {
+                if (q) lptr.push_back((int)lb.size());
+                arc.push_back(jb[q].first);
+            }
+            lb.push_back(jb[q].second);
+        }
+        if (!jb.empty()) lptr.push_back((int)lb.size());
+        arp[i + 1] = (int)arc.size();
+    }
+    f.n_ar = (int)arc.size();
+    CHK(h->upload(&f.arp, arp.data(), arp.size()));
+    CHK(h->upload(&f.arc, arc.data(), arc.size()));
+    CHK(h->upload(&f.ar_lptr, lptr.data(), lptr.size()));
+    CHK(h->upload(&f.ar_lb, lb.data(), lb.size()));
+    const size_t n = (size_t)f.n_ar * f.np * f.npc;
+    if (h->mixed) CHK(h->alloc(&f.AR32, n));
+    else CHK(h->alloc(&f.AR64, n));
+    return XDG_OK;
+}
+
+// (M R) blocks of every level that has them, from the FP64 level matrices
+static void ar_numeric(xdg_handle* h, hipStream_t s) {
+    for (auto& f : h->L) {
+        if (f.AR64)
+            launch_ar_product<double>(s, f.n_ar, f.np, f.npc, f.ar_lptr, f.ar_lb, f.ci, f.ridx,
+                                      f.A64, f.R64, f.AR64);
+        if (f.AR32)
+            launch_ar_product<float>(s, f.n_ar, f.np, f.npc, f.ar_lptr, f.ar_lb, f.ci, f.ridx,
+                                     f.A64, f.R64, f.AR32);
+    }
+}
+
 static int invert_cells(xdg_handle* h, Level& lv, hipStream_t s) {
     HIPCHK(hipMemsetAsync(lv.D64, 0, lv.dsize * sizeof(double), s));
     launch_gather_cells(s, lv.n_cells, lv.np, lv.cp, lv.rp, lv.ci, lv.A64, lv.doff, lv.D64,
@@ -236,6 +282,7 @@ static int numeric_setup(xdg_handle* h, const double* raw) {
     HIPCHK(hipEventRecord(h->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
     for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l], h->s2));
+    ar_numeric(h, h->s2);
     if (h->mixed)
         for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], h->s2);
     HIPCHK(hipEventRecord(h->ev_join, h->s2));
@@ -385,8 +432,10 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
         smooth_from_zero<T>(h, f, h->opt.nu_pre);
     }
     // first post sweep from the kept residual and the coarse correction
-    // (M P from the leading columns), where the level stores them
+    // (M P from the leading columns, or M R for an aggregation), where the
+    // level stores them
     const bool cc = f.t_kind == XDG_T_PTRUNC && P<T>::AP(f) && h->opt.nu_post >= 1;
+    const bool ccd = f.t_kind == XDG_T_DENSE && P<T>::AR(f) && h->opt.nu_post >= 1;
     if (f.t_kind == XDG_T_PTRUNC) {
         xdg::level_spmv<T>(h, f, SPMV_RESID_TRUNC, P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np,
                            cc ? P<T>::r(f) : nullptr);
@@ -396,14 +445,19 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
                                  P<T>::R(f), P<T>::r(f), P<T>::b(c), P<T>::y(f));
     }
     vcycle<T>(h, l + 1);
-    if (cc) {
+    if (cc || ccd) {
         T*& x = P<T>::x(f);
         T*& y = P<T>::y(f);
         const bool last = h->opt.nu_post == 1;
         T* dst = last && out ? out : y;
-        launch_jacobi_cc<T>(h->s, f.n_cells, f.np, c.np, f.cp, f.rp, f.ci, P<T>::AP(f), f.doff,
-                            P<T>::D(f), P<T>::r(f), x, P<T>::x(c), dst, (T)h->opt.omega,
-                            f.next_dir());
+        if (cc)
+            launch_jacobi_cc<T>(h->s, f.n_cells, f.np, c.np, f.cp, f.rp, f.ci, P<T>::AP(f),
+                                f.doff, P<T>::D(f), P<T>::r(f), x, P<T>::x(c), dst,
+                                (T)h->opt.omega, f.next_dir());
+        else
+            launch_jacobi_cc_g<T>(h->s, f.n_cells, f.np, c.np, f.cp, f.arp, f.arc, P<T>::AR(f),
+                                  f.doff, P<T>::D(f), P<T>::r(f), x, P<T>::x(c), f.parent,
+                                  f.ridx, P<T>::R(f), dst, (T)h->opt.omega);
         if (last && out) return;
         std::swap(x, y);
         smooth_more<T>(h, f, h->opt.nu_post - 1, out);
@@ -771,6 +825,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
             CHK(h->upload(&f.chp, chp.data(), chp.size()));
             CHK(h->upload(&f.chi, chi.data(), chi.size()));
             CHK(galerkin_symbolic(h, f, c, tr.parent));
+            if (h->nrhs == 1 && cc_dense_supported(f.np, c.np)) CHK(ar_symbolic(h, f, tr.parent));
             if (h->mixed || h->nrhs == kNrhs) {
                 const int64_t nrr = (int64_t)f.n_rblocks * f.np * c.np;
                 CHK(h->alloc(&f.R32, nrr));
@@ -1407,6 +1462,7 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
         launch_gj_batched(h->s2, (int)ccnt[t], lv.doff, lv.cp, lv.np, lv.max_nc, lv.D64,
                           h->d_err, cl);
     }
+    ar_numeric(h, h->s2);
     if (h->mixed)
         for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], h->s2);
     HIPCHK(hipEventRecord(h->ev_join, h->s2));

@@ -89,6 +89,13 @@ struct Level {
     // (levels with a p-truncation below them and a kernel for the sizes)
     double* AP64 = nullptr;
     float* AP32 = nullptr;
+    // (M R) for the first post sweep after an aggregation coarse correction
+    // (small blocks): BSR pattern over the coarse columns, the fine blocks
+    // summed into every block, values
+    int n_ar = 0;
+    int *arp = nullptr, *arc = nullptr, *ar_lptr = nullptr, *ar_lb = nullptr;
+    double* AR64 = nullptr;
+    float* AR32 = nullptr;
     // direction of the next streaming pass over this level's blocks
     // (alternates; reset at every public call so that results are repeatable)
     bool rev_next = false;
@@ -110,6 +117,7 @@ template <> struct P<double> {
     static double*& y(Level& l) { return l.y64; }
     static double*& r(Level& l) { return l.r64; }
     static double* AP(Level& l) { return l.AP64; }
+    static double* AR(Level& l) { return l.AR64; }
     static SymRows<double> sym(Level& l) {
         SymRows<double> m;
         m.urp = l.urp; m.uci = l.uci; m.lrp = l.lrp; m.lci = l.lci; m.lidx = l.lidx;
@@ -126,6 +134,7 @@ template <> struct P<float> {
     static float*& y(Level& l) { return l.y32; }
     static float*& r(Level& l) { return l.r32; }
     static float* AP(Level& l) { return l.AP32; }
+    static float* AR(Level& l) { return l.AR32; }
     static SymRows<float> sym(Level& l) {
         SymRows<float> m;
         m.urp = l.urp; m.uci = l.uci; m.lrp = l.lrp; m.lci = l.lci; m.lidx = l.lidx;

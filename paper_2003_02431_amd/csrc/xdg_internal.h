@@ -91,6 +91,22 @@ template <typename T>
 void launch_jacobi_cc(hipStream_t s, int n_cells, int np, int npc, const int* cp, const int* rp,
                       const int* ci, const T* AP, const int64_t* doff, const T* D, const T* r1,
                       const T* x1, const T* e, T* xout, T omega, bool rev);
+// First post sweep after an aggregation coarse correction e (npc modes per
+// coarse row): x_out = x1 + R e + omega D^-1 (r1 - (M R) e) on small blocks,
+// (M R) in BSR form (row pointer arp, coarse columns arc, np x npc blocks,
+// column-major); cc_dense_supported: block sizes with the kernel.
+bool cc_dense_supported(int np, int npc);
+template <typename T>
+void launch_jacobi_cc_g(hipStream_t s, int n_cells, int np, int npc, const int* cp,
+                        const int* arp, const int* arc, const T* AR, const int64_t* doff,
+                        const T* D, const T* r1, const T* x1, const T* e, const int* parent,
+                        const int* ridx, const T* R, T* xout, T omega);
+// (M R) blocks: block k sums M_b R_j over the fine blocks b = lb[lptr[k] ..
+// lptr[k+1]-1] (column j = ci[b], transfer block ridx[j] of the table R)
+template <typename Tout>
+void launch_ar_product(hipStream_t s, int64_t n_ar, int np, int npc, const int* lptr,
+                       const int* lb, const int* ci, const int* ridx, const double* A,
+                       const double* R, Tout* AR);
 // AP[b] = the first np*npc entries of block b (its leading npc columns)
 template <typename Tout>
 void launch_leading_columns(hipStream_t s, int64_t nnzb, int np, int npc, const double* A,
