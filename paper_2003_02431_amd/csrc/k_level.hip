@@ -354,6 +354,69 @@ __global__ __launch_bounds__(256) void k_jacobi(int n_cells, int np_rt, const in
     }
 }
 
+// CG update of x and r (alpha = scal[i_rz] / scal[i_pq]) fused with the first
+// sweep from zero of the next V-cycle on the new residual: per cell, x += alpha
+// p, r -= alpha q, x1 = omega D^-1 r (the same product as k_jacobi<FIRST>), and
+// the workgroup's partial of r . r (lanes, then the four cells in order) in
+// dpart[blockIdx.x].
+template <int NP>
+__global__ __launch_bounds__(256) void k_cg_update_first(int n_cells,
+                                                         const int* __restrict__ cell_ptr,
+                                                         const int64_t* __restrict__ doff,
+                                                         const double* __restrict__ D,
+                                                         const double* __restrict__ scal,
+                                                         int i_rz, int i_pq,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ q,
+                                                         double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         double* __restrict__ x1, double omega,
+                                                         double* __restrict__ dpart) {
+    using R = RowCfg<double, NP, (NP >= 16)>;
+    constexpr int V = R::VEC;
+    __shared__ double res[4][kMaxCell];
+    __shared__ double wsum[4];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int cell = uniform(blockIdx.x * 4 + w);
+    const double alpha = scal[i_rz] / scal[i_pq];
+    double dsum = 0.0;
+    if (cell < n_cells) {
+        const int r0 = uniform(cell_ptr[cell]), r1 = uniform(cell_ptr[cell + 1]);
+        const int nc = (r1 - r0) * NP;
+        const int64_t base = (int64_t)r0 * NP;
+        for (int o = lane; o < nc; o += 64) {
+            x[base + o] += alpha * p[base + o];
+            const double ro = r[base + o] - alpha * q[base + o];
+            r[base + o] = ro;
+            res[w][o] = ro;
+            dsum += ro * ro;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double* Dc = D + doff[cell];
+        if (nc <= 64 * V) {
+            double acc[V];
+            dense_apply<double, V>(Dc, nc, res[w], lane, acc);
+            if (lane < nc / V) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) x1[base + lane * V + v] = omega * acc[v];
+            }
+        } else {
+            for (int o = lane; o < nc; o += 64) {
+                double acc = 0;
+                for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * res[w][c];
+                x1[base + o] = omega * acc;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off, 64);
+    if (lane == 0) wsum[w] = dsum;
+    __syncthreads();
+    if (threadIdx.x == 0) dpart[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
 // ---------------------------------------------------------------------------
 // Symmetric level matrix kept as its diagonal and upper blocks (column >= row,
 // the SIP matrix being symmetric).  Row i's product is its upper stream
@@ -1245,6 +1308,23 @@ void launch_jacobi_sym(hipStream_t s, int n_cells, const int* cp, const SymRows<
 
 bool cc_supported(int np, int npc) { return (np == 20 || np == 35) && npc == 4; }
 bool cc_dense_supported(int np, int npc) { return np == 4 && npc == 4; }
+
+bool launch_cg_update_first(hipStream_t s, int n_cells, int np, const int* cp,
+                            const int64_t* doff, const double* D, const double* scal, int i_rz,
+                            int i_pq, int i_rr, const double* p, const double* q, double* x,
+                            double* r, double* x1, double omega, double* partial) {
+    const unsigned nb = nblk(n_cells, 4);
+    if (np == 20)
+        k_cg_update_first<20><<<nb, 256, 0, s>>>(n_cells, cp, doff, D, scal, i_rz, i_pq, p, q, x,
+                                                 r, x1, omega, partial);
+    else if (np == 35)
+        k_cg_update_first<35><<<nb, 256, 0, s>>>(n_cells, cp, doff, D, scal, i_rz, i_pq, p, q, x,
+                                                 r, x1, omega, partial);
+    else
+        return false;
+    launch_dot_final(s, partial, (int)nb, const_cast<double*>(scal) + i_rr);
+    return true;
+}
 
 template <typename T>
 void launch_jacobi_cc_g(hipStream_t s, int n_cells, int np, int npc, const int* cp,

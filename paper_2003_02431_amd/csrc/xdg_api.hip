@@ -425,8 +425,16 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
     Level& c = h->L[l + 1];
     bool learned = false;
     if constexpr (std::is_same<T, double>::value) learned = l == 0 && xdg::learned_active(h);
+    bool x1_done = false;
+    if constexpr (std::is_same<T, double>::value) {
+        x1_done = l == 0 && h->x1_ready;
+        if (l == 0) h->x1_ready = false;
+    }
     if (learned) {
         xdg::learned_first_sweep(h, f);
+        smooth_more<T>(h, f, h->opt.nu_pre - 1);
+    } else if (x1_done) {
+        f.next_dir();                    // the fused sweep counts as the pass
         smooth_more<T>(h, f, h->opt.nu_pre - 1);
     } else {
         smooth_from_zero<T>(h, f, h->opt.nu_pre);
@@ -471,9 +479,11 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
     smooth_more<T>(h, f, h->opt.nu_post, out);
 }
 
-// every public call starts its streaming passes in ascending order
+// every public call starts its streaming passes in ascending order (and with
+// no first sweep carried over from an earlier solve)
 static void reset_dirs(xdg_handle* h) {
     for (auto& lv : h->L) lv.rev_next = false;
+    h->x1_ready = false;
 }
 
 // z = B r for FP64 vectors, using the handle's precision for the cycle
@@ -1039,6 +1049,11 @@ static int true_relres(xdg_handle* h, const double* b, const double* x, double* 
 // and the new direction is made A-orthogonal to the previous one,
 // beta = -z.q_old / p_old.q_old; in exact arithmetic with a fixed symmetric
 // preconditioner it is PCG.
+// the fused update's workgroup partials fit the reduction buffer
+static bool n_cells_ok(const Level& f) {
+    return (int64_t)(f.n_cells + 3) / 4 <= (int64_t)kPartDoubles;
+}
+
 static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int cap,
                     int* iters) {
     Level& f = h->L[0];
@@ -1072,7 +1087,18 @@ static int solve_cg(xdg_handle* h, const double* b, double* x, double* hist, int
         // size allows, and r . r formed in the update of x and r
         xdg::level_spmv_dot(h, f, h->p, h->q, h->scal + S_PQ);
         if (flex) launch_dot(s, n, h->p, h->r, h->part, h->scal + cur);   // alpha numerator
-        launch_cg_update_xr_dot(s, n, h->scal, cur, S_PQ, S_RR, h->p, h->q, x, h->r, h->part);
+        // the update fused with the next cycle's first level-0 sweep where the
+        // cycle would start with it (FP64 block Jacobi, pre-sweeps, a level
+        // below); if r converges the sweep was not needed
+        const bool fuse = !flex && h->opt.smoother == XDG_JACOBI && h->opt.nu_pre >= 1 &&
+                          h->L.size() > 1 && n_cells_ok(f) &&
+                          launch_cg_update_first(s, f.n_cells, f.np, f.cp, f.doff, f.D64, h->scal,
+                                                 cur, S_PQ, S_RR, h->p, h->q, x, h->r, f.x64,
+                                                 h->opt.omega, h->part);
+        if (!fuse)
+            launch_cg_update_xr_dot(s, n, h->scal, cur, S_PQ, S_RR, h->p, h->q, x, h->r,
+                                    h->part);
+        h->x1_ready = fuse;
         CHK(read_scalars(h, S_RR, 2));
         HIPCHK(hipGetLastError());
         *iters = k;

@@ -194,6 +194,9 @@ struct xdg_handle {
     int *proj_rp = nullptr, *proj_ci = nullptr;
     double* proj_A = nullptr;
     float guard = 4.0f;             // |proposal| / |Jacobi step| above this: plain step
+    // level 0's first pre-smoothing sweep of the next FP64 V-cycle already
+    // done by the CG update (set by the solver, consumed by the cycle)
+    bool x1_ready = false;
     bool learned_ready = false;     // weights and features present
     bool learned_off = false;       // solver-level fallback taken in this solve
     int learned_fallbacks = 0;      // solver-level fallbacks (all solves)

@@ -107,6 +107,13 @@ template <typename Tout>
 void launch_ar_product(hipStream_t s, int64_t n_ar, int np, int npc, const int* lptr,
                        const int* lb, const int* ci, const int* ridx, const double* A,
                        const double* R, Tout* AR);
+// CG update (x += alpha p, r -= alpha q) fused with the first sweep from zero
+// of the next V-cycle on level 0 (x1 = omega D^-1 r) and scal[i_rr] = r . r;
+// false (nothing launched) for block sizes without the kernel (np 20, 35)
+bool launch_cg_update_first(hipStream_t s, int n_cells, int np, const int* cp,
+                            const int64_t* doff, const double* D, const double* scal, int i_rz,
+                            int i_pq, int i_rr, const double* p, const double* q, double* x,
+                            double* r, double* x1, double omega, double* partial);
 // AP[b] = the first np*npc entries of block b (its leading npc columns)
 template <typename Tout>
 void launch_leading_columns(hipStream_t s, int64_t nnzb, int np, int npc, const double* A,
