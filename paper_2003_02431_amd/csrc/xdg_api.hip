@@ -1,7 +1,9 @@
 // C-ABI of libxdg: hierarchy construction and the solver loops (host side).
 // Every arithmetic step runs in the kernels of k_level.hip / k_setup.hip /
 // k_blas.hip; this file only validates input, does the integer bookkeeping of
-// the Galerkin sparsity pattern, and sequences launches on the handle's stream.
+// the sparsity patterns, and sequences launches on the handle's stream (the
+// numeric set-up also on an internal side stream, joined back by an event
+// before anything reads its results).
 #include <numeric>
 
 #include <mutex>
