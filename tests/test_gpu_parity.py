@@ -207,6 +207,41 @@ def test_pcg_solve(name, torch):
     assert rck == B.XDG_ENOCONV and itk == ito and ek <= 1e-11
 
 
+@pytest.mark.parametrize("name", ["c2n8", "c2n16"])
+def test_calls_after_a_solve(name, torch):
+    """The FP64 CG fuses its x/r update with the next cycle's first level-0
+    sweep and lets the cycle skip that sweep; a solve that stops right after
+    such an update must not leak this into later calls: xdg_vcycle and
+    xdg_smooth after a solve equal the same calls on a fresh handle, bit for
+    bit, and a second solve repeats the first."""
+    from paper_2003_02431_amd import binding as B
+    pr, H, S = _case(name, torch)
+    n = S.level_len(0)
+    r = S.vec(0, np.random.default_rng(5).uniform(-1, 1, n))
+    x = S.vec(0)
+    rc1, it1, fr1, _ = B.xdg_solve(S.h, S.vec(0, pr.b), x)
+    x1 = x.cpu().numpy().copy()
+    z = S.vec(0)
+    B.xdg_vcycle(S.h, r, z)
+    F = B.Solver(pr, B.options(rtol=1e-10, maxit=600))
+    zf = F.vec(0)
+    B.xdg_vcycle(F.h, F.vec(0, r.cpu().numpy()), zf)
+    d = float(np.max(np.abs(z.cpu().numpy() - zf.cpu().numpy())))
+    xs = S.vec(0, np.zeros(n))
+    B.xdg_smooth(S.h, 0, r, xs, 1)
+    xsf = F.vec(0, np.zeros(n))
+    B.xdg_smooth(F.h, 0, F.vec(0, r.cpu().numpy()), xsf, 1)
+    ds = float(np.max(np.abs(xs.cpu().numpy() - xsf.cpu().numpy())))
+    x.zero_()
+    rc2, it2, fr2, _ = B.xdg_solve(S.h, S.vec(0, pr.b), x)
+    dx = float(np.max(np.abs(x.cpu().numpy() - x1)))
+    F.close()
+    _log(f"  {name}: after a solve ({it1} it): V-cycle max diff {d:.1e}, sweep {ds:.1e}, "
+         f"second solve {it2} it, max diff {dx:.1e}")
+    assert rc1 == 0 and rc2 == 0 and it1 == it2
+    assert d == 0.0 and ds == 0.0 and dx == 0.0
+
+
 @pytest.mark.parametrize("name", ["c1", "c2n16"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fgmres_solve(name, prec, torch):
