@@ -167,9 +167,9 @@ int xdg_vcycle(xdg_handle *h, const double *r_dev, double *z_dev);
  * (32 MiB) that the library reserves once per device and keeps until the
  * process ends.  The call makes no hipMalloc, hipFree or other allocating
  * call.  Single-column handles with the block-Jacobi smoother only (else
- * XDG_EINVAL).  The cycle needs about four doubles per level-0 unknown in
- * FP64 and two in the FP32 cycle (the 32^3 p = 3 workload: about 2.7
- * million in FP64); a larger one returns XDG_EINVAL.  Every call on one
+ * XDG_EINVAL).  The cycle needs about five doubles per level-0 unknown in
+ * FP64 and two and a half in the FP32 cycle (the 32^3 p = 3 workload: about
+ * 3.3 million in FP64); a larger one returns XDG_EINVAL.  Every call on one
  * device shares the array and leaves its contents behind: calls that overlap
  * on one device (other streams or threads) race, and the caller must order
  * them.  r_dev read, z_dev overwritten (level-0 vectors). */
