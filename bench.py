@@ -4,8 +4,9 @@ Workload: 3D SIP Poisson, p = 3 (20 modes/species/cell), 32^3 cut grid on
 [-1,1]^3, sphere r = 0.6 with seeded centre jitter, diffusivity 1 | 1000,
 alpha = 0.1, RHS ~ U[-1,1] per coefficient, 4-level aggregation + p multigrid
 V-cycle (p3 -> p1 -> 16^3 -> 8^3 aggregates) with damped block Jacobi (1 pre /
-1 post, omega 0.9: the fastest measured setting; 2 / 2 at omega 0.7 is
---nu 2 --omega 0.7), FP64 CG.
+1 post on the finest level, 4 / 4 on the levels below, omega 0.9: the fastest
+measured setting; 2 / 2 everywhere at omega 0.7 is --nu 2 --omega 0.7
+--nu-coarse 0), FP64 CG.
 
 One step = the whole hot path on device-resident input: numeric hierarchy
 set-up from the level-0 values (Galerkin products, cell-block and coarsest
@@ -96,7 +97,7 @@ def time_spmv(torch, B, S, level, reps=50):
     return e0.elapsed_time(e1) / reps * 1e-3   # seconds per launch
 
 
-def cpu_baseline(pr, omega=0.7, nu=2):
+def cpu_baseline(pr, omega=0.7, nu=2, nu_coarse=0):
     """The plain-loop C++17/OpenMP oracle as it stands, on every host core:
     its hierarchy set-up (Galerkin products, Cholesky cell-block and coarsest
     factorisations) plus its PCG solve of the same problem to rel.res 1e-8,
@@ -108,7 +109,7 @@ def cpu_baseline(pr, omega=0.7, nu=2):
         mg_omp.build()
     cores = mg_omp.threads()
     t0 = time.perf_counter()
-    O = mg_omp.OmpHierarchy(pr, omega=omega, nu=nu)
+    O = mg_omp.OmpHierarchy(pr, omega=omega, nu=nu, nu_coarse=nu_coarse)
     t1 = time.perf_counter()
     x8, _, it8 = O.pcg(pr.b, rtol=1e-8, maxit=2000)
     t2 = time.perf_counter()
@@ -386,7 +387,7 @@ def bench_moving(args):
     log(f"[bench-moving] two time levels generated in {time.time() - t0:.1f}s: rows "
         f"{pr0.n_rows} -> {pr1.n_rows}")
     opt = B.options(krylov=B.XDG_CG, rtol=1e-8, maxit=1000, nu_pre=args.nu, nu_post=args.nu,
-                    omega=args.omega)
+                    omega=args.omega, nu_coarse=args.nu_coarse)
     S0 = B.Solver(pr0, opt)
     x0 = S0.vec(0)
     B.xdg_solve(S0.h, S0.vec(0, pr0.b), x0)
@@ -449,6 +450,9 @@ def main():
     ap.add_argument("--nu", type=int, default=1,
                     help="block-Jacobi sweeps before and after the coarse correction")
     ap.add_argument("--omega", type=float, default=0.9, help="Jacobi damping")
+    ap.add_argument("--nu-coarse", type=int, default=4,
+                    help="block-Jacobi sweeps before and after the coarse correction on the "
+                         "levels below the finest (0: --nu there too)")
     ap.add_argument("--hier", default="p1h", choices=["p1h", "h3p1", "hp", "h2p"],
                     help="coarse-level sequence of the 32^3 workload (xdg_inputs.problems."
                          "hierarchy)")
@@ -488,7 +492,8 @@ def main():
     log(f"[bench] generated rows={pr.n_rows} nnzb={pr.col_idx.size} in {time.time() - t0:.1f}s")
 
     def opts(**kw):
-        return B.options(nu_pre=args.nu, nu_post=args.nu, omega=args.omega, **kw)
+        return B.options(nu_pre=args.nu, nu_post=args.nu, omega=args.omega,
+                         nu_coarse=args.nu_coarse, **kw)
 
     opt8 = opts(krylov=B.XDG_CG, rtol=1e-8, maxit=1000)
     S = B.Solver(pr, opt8)
@@ -736,7 +741,8 @@ def main():
     cpu, errs = None, {}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: the C++ oracle's set-up and PCG solve to rel.res 1e-8")
-        cpu, xstar, it_star = cpu_baseline(pr, omega=args.omega, nu=args.nu)
+        cpu, xstar, it_star = cpu_baseline(pr, omega=args.omega, nu=args.nu,
+                                           nu_coarse=args.nu_coarse)
         log(f"[bench] cpu baseline {cpu}")
         xs_dev = torch.as_tensor(xstar).cuda()
         ns = torch.linalg.norm(xs_dev)
@@ -769,7 +775,9 @@ def main():
                    "level_dofs": [int(pr.n_rows * pr.np)] + [int(T["n_rows_c"] * T["np_c"])
                                                              for T in pr.transfers],
                    "krylov": "CG",
-                   "smoother": f"block-Jacobi {args.nu}+{args.nu} omega={args.omega}",
+                   "smoother": f"block-Jacobi {args.nu}+{args.nu} omega={args.omega}"
+                               + (f", {args.nu_coarse}+{args.nu_coarse} below the finest level"
+                                  if args.nu_coarse else ""),
                    "c_eta": args.c_eta or problems_c_eta(), "seed": args.seed},
         "iters_to_1e-8": int(np.median(its)),
         "setup_ms": round(setup_ms, 3),

@@ -105,6 +105,11 @@ typedef struct {
                               /* values of the lower blocks are not read by the */
                               /* solve (set-up and xdg_get_level_matrix use     */
                               /* all blocks).  0: every block is read.          */
+    int32_t nu_coarse;        /* > 0: block-Jacobi sweeps before and after the  */
+                              /* coarse correction on every level below the     */
+                              /* finest in the V-cycle of xdg_vcycle/xdg_solve  */
+                              /* (CG, FGMRES; the orthonormalisation MG keeps   */
+                              /* nu_pre/nu_post); 0: nu_pre/nu_post there too   */
 } xdg_options;
 
 /* Copies the level-0 system and transfers to the device, forms every coarse

@@ -84,8 +84,11 @@ class Hierarchy:
     """Galerkin multigrid hierarchy from the level-0 matrix and transfers."""
 
     def __init__(self, row_ptr, col_idx, val, cell_ptr, transfers, omega=0.7, nu_pre=2,
-                 nu_post=2):
+                 nu_post=2, nu_coarse=0):
+        # nu_coarse > 0: that many sweeps before and after the coarse
+        # correction on every level below the finest (else nu_pre / nu_post)
         self.omega, self.nu_pre, self.nu_post = omega, nu_pre, nu_post
+        self.nu_coarse = nu_coarse
         Np = val.shape[1]
         self.A = [block_matrix(row_ptr, col_idx, val)]
         self.np = [Np]
@@ -116,10 +119,13 @@ class Hierarchy:
         if level == self.nlev - 1:
             return self.coarse_solve(r)
         A, D = self.A[level], self.Dinv[level]
-        x = jacobi(A, D, r, np.zeros_like(r), self.omega, self.nu_pre)
+        coarse = level > 0 and self.nu_coarse > 0
+        nu_pre = self.nu_coarse if coarse else self.nu_pre
+        nu_post = self.nu_coarse if coarse else self.nu_post
+        x = jacobi(A, D, r, np.zeros_like(r), self.omega, nu_pre)
         rc = self.R[level].T @ (r - A @ x)
         x = x + self.R[level] @ self.vcycle(rc, level + 1)
-        return jacobi(A, D, r, x, self.omega, self.nu_post)
+        return jacobi(A, D, r, x, self.omega, nu_post)
 
     def lambda_max_DinvA(self, level, iters=200, seed=0):
         """Power-iteration estimate of the largest eigenvalue of D^{-1} A
@@ -211,8 +217,8 @@ def fgmres(A, b, precond, rtol=1e-8, restart=30, maxit=500, x0=None):
     return x, hist, it
 
 
-def hierarchy_of(pr, omega=0.7, nu=2):
+def hierarchy_of(pr, omega=0.7, nu=2, nu_coarse=0):
     """Hierarchy of a generated problem (any object carrying row_ptr, col_idx,
     val, cell_ptr and transfers)."""
     return Hierarchy(pr.row_ptr, pr.col_idx, pr.val, pr.cell_ptr, pr.transfers,
-                     omega=omega, nu_pre=nu, nu_post=nu)
+                     omega=omega, nu_pre=nu, nu_post=nu, nu_coarse=nu_coarse)

@@ -179,6 +179,7 @@ struct mgo_handle {
     int64_t coarse_n = 0;
     double omega = 0.7;
     int nu_pre = 2, nu_post = 2;
+    int nu_coarse = 0;              // > 0: sweeps on every level below the finest
     std::vector<double> partial;    // per-thread partial sums of inner products
 };
 
@@ -231,8 +232,9 @@ void vcycle(mgo_handle* h, int l, const double* r, double* z) {
         return;
     }
     Level& cl = h->L[l + 1];
+    const bool coarse = l > 0 && h->nu_coarse > 0;
     std::fill(z, z + n, 0.0);
-    jacobi(h, lv, r, z, h->nu_pre);
+    jacobi(h, lv, r, z, coarse ? h->nu_coarse : h->nu_pre);
     spmv(lv.A, z, lv.y.data());
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) lv.r[i] = r[i] - lv.y[i];
@@ -241,7 +243,7 @@ void vcycle(mgo_handle* h, int l, const double* r, double* z) {
     spmv(lv.R, cl.x.data(), lv.y.data());
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) z[i] += lv.y[i];
-    jacobi(h, lv, r, z, h->nu_post);
+    jacobi(h, lv, r, z, coarse ? h->nu_coarse : h->nu_post);
 }
 
 }  // namespace
@@ -253,6 +255,10 @@ int mgo_threads(void) { return omp_get_max_threads(); }
 void mgo_set_threads(int n) {
     if (n > 0) omp_set_num_threads(n);
 }
+
+// sweeps before and after the coarse correction on the levels below the
+// finest (0: the finest level's counts)
+void mgo_set_coarse_sweeps(mgo_handle* h, int32_t nu_coarse) { h->nu_coarse = nu_coarse; }
 
 // Level-0 block matrix (val row-major per block) and its smoother cells.
 mgo_handle* mgo_new(int32_t n_rows, int32_t np, int32_t nnzb, const int32_t* row_ptr,

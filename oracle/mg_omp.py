@@ -45,6 +45,7 @@ def lib():
         sig = {
             "mgo_threads": ([], C.c_int),
             "mgo_set_threads": ([C.c_int], None),
+            "mgo_set_coarse_sweeps": ([vp, i32], None),
             "mgo_new": ([i32, i32, i32, i32p, i32p, f64p, i32, i32p, f64, i32, i32], vp),
             "mgo_add_transfer": ([vp, i32, i32, i32, i32p, f64p, i32, i32p], None),
             "mgo_setup": ([vp], C.c_int),
@@ -81,7 +82,7 @@ def set_threads(n):
 class OmpHierarchy:
     """The multigrid hierarchy of a generated problem in the C++ oracle."""
 
-    def __init__(self, pr, omega=0.7, nu=2):
+    def __init__(self, pr, omega=0.7, nu=2, nu_coarse=0):
         L = lib()
         self._keep = []
         k = lambda a, dt: self._keep.append(np.ascontiguousarray(a, dtype=dt)) or self._keep[-1]
@@ -90,6 +91,7 @@ class OmpHierarchy:
         self.h = C.c_void_p(L.mgo_new(len(rp) - 1, val.shape[1], len(ci), _p(rp, C.c_int32),
                                       _p(ci, C.c_int32), _p(val, C.c_double), len(cp) - 1,
                                       _p(cp, C.c_int32), omega, nu, nu))
+        L.mgo_set_coarse_sweeps(self.h, int(nu_coarse))
         for T in pr.transfers:
             par = k(T["parent"], np.int32)
             cpc = k(T["cell_ptr_c"], np.int32)

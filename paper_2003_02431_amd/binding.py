@@ -57,7 +57,7 @@ class xdg_options(C.Structure):
     _fields_ = [("krylov", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("precision", C.c_int32),
                 ("smoother", C.c_int32), ("nrhs", C.c_int32), ("rtol", C.c_double),
-                ("omega", C.c_double), ("symmetric", C.c_int32)]
+                ("omega", C.c_double), ("symmetric", C.c_int32), ("nu_coarse", C.c_int32)]
 
 
 def _load():
@@ -178,9 +178,9 @@ def _vec(h, level, t, what):
 
 
 def options(krylov=XDG_CG, restart=30, maxit=500, nu_pre=2, nu_post=2, precision=XDG_FP64,
-            smoother=XDG_JACOBI, nrhs=1, rtol=1e-10, omega=0.7, symmetric=1):
+            smoother=XDG_JACOBI, nrhs=1, rtol=1e-10, omega=0.7, symmetric=1, nu_coarse=0):
     return xdg_options(krylov, restart, maxit, nu_pre, nu_post, precision, smoother, nrhs,
-                       rtol, omega, symmetric)
+                       rtol, omega, symmetric, nu_coarse)
 
 
 def xdg_create(row_ptr, col_idx, val, cell_ptr, transfers, opt, stream=None):

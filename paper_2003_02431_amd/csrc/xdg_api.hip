@@ -432,20 +432,21 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
         x1_done = l == 0 && h->x1_ready;
         if (l == 0) h->x1_ready = false;
     }
+    const int nu_pre = xdg::sweeps_pre(h, l), nu_post = xdg::sweeps_post(h, l);
     if (learned) {
         xdg::learned_first_sweep(h, f);
-        smooth_more<T>(h, f, h->opt.nu_pre - 1);
+        smooth_more<T>(h, f, nu_pre - 1);
     } else if (x1_done) {
         f.next_dir();                    // the fused sweep counts as the pass
-        smooth_more<T>(h, f, h->opt.nu_pre - 1);
+        smooth_more<T>(h, f, nu_pre - 1);
     } else {
-        smooth_from_zero<T>(h, f, h->opt.nu_pre);
+        smooth_from_zero<T>(h, f, nu_pre);
     }
     // first post sweep from the kept residual and the coarse correction
     // (M P from the leading columns, or M R for an aggregation), where the
     // level stores them
-    const bool cc = f.t_kind == XDG_T_PTRUNC && P<T>::AP(f) && h->opt.nu_post >= 1;
-    const bool ccd = f.t_kind == XDG_T_DENSE && P<T>::AR(f) && h->opt.nu_post >= 1;
+    const bool cc = f.t_kind == XDG_T_PTRUNC && P<T>::AP(f) && nu_post >= 1;
+    const bool ccd = f.t_kind == XDG_T_DENSE && P<T>::AR(f) && nu_post >= 1;
     if (f.t_kind == XDG_T_PTRUNC) {
         xdg::level_spmv<T>(h, f, SPMV_RESID_TRUNC, P<T>::x(f), P<T>::b(f), P<T>::b(c), c.np,
                            cc ? P<T>::r(f) : nullptr);
@@ -458,7 +459,7 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
     if (cc || ccd) {
         T*& x = P<T>::x(f);
         T*& y = P<T>::y(f);
-        const bool last = h->opt.nu_post == 1;
+        const bool last = nu_post == 1;
         T* dst = last && out ? out : y;
         if (cc)
             launch_jacobi_cc<T>(h->s, f.n_cells, f.np, c.np, f.cp, f.rp, f.ci, P<T>::AP(f),
@@ -470,7 +471,7 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
                                   f.ridx, P<T>::R(f), dst, (T)h->opt.omega);
         if (last && out) return;
         std::swap(x, y);
-        smooth_more<T>(h, f, h->opt.nu_post - 1, out);
+        smooth_more<T>(h, f, nu_post - 1, out);
         return;
     }
     if (f.t_kind == XDG_T_PTRUNC)
@@ -478,7 +479,7 @@ static void vcycle(xdg_handle* h, int l, T* out = nullptr) {
     else
         launch_prolong_dense<T>(h->s, f.n_rows, f.np, c.np, f.parent, f.ridx, P<T>::R(f), P<T>::x(c),
                                 P<T>::x(f));
-    smooth_more<T>(h, f, h->opt.nu_post, out);
+    smooth_more<T>(h, f, nu_post, out);
 }
 
 // every public call starts its streaming passes in ascending order (and with
@@ -702,6 +703,7 @@ static int create_impl(xdg_handle* h, const xdg_matrix* A0, int32_t n_levels,
     if (opt->nrhs == kNrhs) CHK(mrhs_validate(opt, A0->np, T, n_levels));
     if (opt->symmetric != 0 && opt->symmetric != 1)
         return fail(XDG_EINVAL, "xdg_create: symmetric must be 0 or 1");
+    if (opt->nu_coarse < 0) return fail(XDG_EINVAL, "xdg_create: nu_coarse must be >= 0");
     SymLists sl;
     const bool use_sym = opt->symmetric == 1 && opt->nrhs == 1 && A0->np == kSymNp;
     if (use_sym && !sym_lists(A0->n_rows, A0->row_ptr, A0->col_idx, sl))

@@ -243,6 +243,14 @@ int mrhs_solve(xdg_handle* h, const double* B, double* X, double* hist, int cap,
 }  // namespace xdg
 
 namespace xdg {
+// block-Jacobi sweeps before / after the coarse correction on level l of the
+// V-cycle (levels below the finest take nu_coarse when it is set)
+inline int sweeps_pre(const xdg_handle* h, int l) {
+    return l > 0 && h->opt.nu_coarse > 0 ? h->opt.nu_coarse : h->opt.nu_pre;
+}
+inline int sweeps_post(const xdg_handle* h, int l) {
+    return l > 0 && h->opt.nu_coarse > 0 ? h->opt.nu_coarse : h->opt.nu_post;
+}
 // the level's operator on its storage (all blocks, or the symmetric upper
 // blocks); every call flips the level's streaming direction
 // (SPMV_RESID_TRUNC: yfull != nullptr also keeps the whole residual)

@@ -57,7 +57,7 @@ void vcycle_m(xdg_handle* h, int l) {
         return;
     }
     Level& c = h->L[l + 1];
-    sweeps_m(h, f, true, h->opt.nu_pre);
+    sweeps_m(h, f, true, xdg::sweeps_pre(h, l));
     if (f.t_kind == XDG_T_PTRUNC) {
         launch_spmm<float, float, float>(h->s, SPMV_RESID_TRUNC, f.n_rows, f.np, f.rp, f.ci,
                                          f.Ap32, f.xm, f.bm, c.bm, c.np);
@@ -73,7 +73,7 @@ void vcycle_m(xdg_handle* h, int l) {
     else
         launch_prolong_dense_m<float>(h->s, f.n_rows, f.np, c.np, f.parent, f.ridx, f.R32, c.xm,
                                       f.xm);
-    sweeps_m(h, f, false, h->opt.nu_post);
+    sweeps_m(h, f, false, xdg::sweeps_post(h, l));
 }
 
 // z = B v on 16 FP32 columns

@@ -207,6 +207,39 @@ def test_pcg_solve(name, torch):
     assert rck == B.XDG_ENOCONV and itk == ito and ek <= 1e-11
 
 
+@pytest.mark.parametrize("name", ["c2n16", "c2n8hp", "c4n8p4"])
+def test_coarse_sweeps(name, torch):
+    """nu_coarse = 3 (three sweeps before and after the coarse correction on
+    every level below the finest, one on level 0, omega 0.9: the benchmark's
+    cycle): one V-cycle and the PCG iterate after the oracle's iteration count
+    against the oracle's hierarchy with the same counts."""
+    from oracle import mg
+    from paper_2003_02431_amd import binding as B
+    pr, _, _ = _case(name, torch)
+    H = mg.hierarchy_of(pr, omega=0.9, nu=1, nu_coarse=3)
+    S = B.Solver(pr, B.options(rtol=1e-10, maxit=600, nu_pre=1, nu_post=1, omega=0.9,
+                               nu_coarse=3))
+    n = S.level_len(0)
+    r = np.random.default_rng(11).uniform(-1, 1, n)
+    z = S.vec(0)
+    B.xdg_vcycle(S.h, S.vec(0, r), z)
+    kappa = np.linalg.cond(H.A[-1].toarray())
+    ev = _rel(z.cpu().numpy(), H.vcycle(r))
+    b = np.asarray(pr.b).reshape(-1)
+    xo, ho, ito = mg.pcg(H.A[0], b, H.vcycle, rtol=1e-10, maxit=600)
+    B.xdg_set_tolerance(S.h, 1e-300, ito)
+    xk = S.vec(0)
+    rck, itk, _, _ = B.xdg_solve(S.h, S.vec(0, b), xk)
+    ek = _rel(xk.cpu().numpy(), xo)
+    H1 = mg.hierarchy_of(pr, omega=0.9, nu=1)
+    _, _, it1 = mg.pcg(H1.A[0], b, H1.vcycle, rtol=1e-10, maxit=600)
+    S.close()
+    _log(f"  {name}: nu_coarse 3: V-cycle rel err {ev:.2e} (coarse kappa {kappa:.1e}); "
+         f"PCG iterate {itk} (oracle {ito}, one sweep everywhere {it1}) rel diff {ek:.2e}")
+    assert ev <= _kappa_tol(kappa)
+    assert rck == B.XDG_ENOCONV and itk == ito and ek <= 1e-11
+
+
 @pytest.mark.parametrize("name", ["c2n8", "c2n16"])
 def test_calls_after_a_solve(name, torch):
     """The FP64 CG fuses its x/r update with the next cycle's first level-0
@@ -500,7 +533,7 @@ def test_update_cells_equals_full_update(name, torch):
 
 
 # the benchmark's smoother on the 32^3 workload (bench.py defaults)
-BENCH_NU, BENCH_OMEGA = 1, 0.9
+BENCH_NU, BENCH_OMEGA, BENCH_NU_COARSE = 1, 0.9, 4
 
 
 def test_full_size_sampled(torch):
@@ -515,7 +548,7 @@ def test_full_size_sampled(torch):
     pr = problems.c2(seed=0, n=32, verbose=True)
     A = mg.block_matrix(pr.row_ptr, pr.col_idx, pr.val)
     S = B.Solver(pr, B.options(rtol=1e-10, maxit=600, nu_pre=BENCH_NU, nu_post=BENCH_NU,
-                               omega=BENCH_OMEGA))
+                               omega=BENCH_OMEGA, nu_coarse=BENCH_NU_COARSE))
     rng = np.random.default_rng(15)
     x = rng.uniform(-1, 1, A.shape[0])
     y = S.vec(0)
@@ -525,7 +558,7 @@ def test_full_size_sampled(torch):
     ref = A[idx] @ x
     assert _rel(y.cpu().numpy()[idx], ref) <= 1e-13
     _log("[gpu-parity] oracle hierarchy at 32^3")
-    H = mg.hierarchy_of(pr, omega=BENCH_OMEGA, nu=BENCH_NU)
+    H = mg.hierarchy_of(pr, omega=BENCH_OMEGA, nu=BENCH_NU, nu_coarse=BENCH_NU_COARSE)
     for l in range(1, H.nlev):
         rp, ci, val = B.xdg_get_level_matrix(S.h, l)
         G = mg.block_matrix(rp, ci, val)
@@ -567,7 +600,7 @@ def test_full_size_sampled(torch):
     from oracle import mg_omp
     if not os.path.exists(mg_omp.LIB):
         mg_omp.build()
-    O = mg_omp.OmpHierarchy(pr, omega=BENCH_OMEGA, nu=BENCH_NU)
+    O = mg_omp.OmpHierarchy(pr, omega=BENCH_OMEGA, nu=BENCH_NU, nu_coarse=BENCH_NU_COARSE)
     xo, ho, ito = O.pcg(pr.b, rtol=1e-10, maxit=600)
     O.close()
     B.xdg_set_tolerance(S.h, 1e-300, ito)

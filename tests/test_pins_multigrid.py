@@ -123,28 +123,31 @@ def test_p_level_is_leading_subblock(pr2):
     assert np.array_equal(lead, H.A[1].toarray())
 
 
-def _vcycle_dense(H, level):
-    """B_l = (I - S^nu2 (I - R B_{l+1} R^T A) S^nu1) A^{-1}, S = I - w D^{-1} A."""
+def _vcycle_dense(H, level, sweeps):
+    """B_l = (I - S^nu (I - R B_{l+1} R^T A) S^nu) A^{-1}, S = I - w D^{-1} A,
+    nu = sweeps[l] (the same count before and after the coarse correction)."""
     A = H.A[level].toarray()
     if level == H.nlev - 1:
         return np.linalg.inv(A)
     I = np.eye(A.shape[0])
     S = I - H.omega * H.Dinv[level].toarray() @ A
     R = H.R[level].toarray()
-    Bc = _vcycle_dense(H, level + 1)
-    E = np.linalg.matrix_power(S, H.nu_post) @ (I - R @ Bc @ R.T @ A) @ \
-        np.linalg.matrix_power(S, H.nu_pre)
+    Bc = _vcycle_dense(H, level + 1, sweeps)
+    Sn = np.linalg.matrix_power(S, sweeps[level])
+    E = Sn @ (I - R @ Bc @ R.T @ A) @ Sn
     return (I - E) @ np.linalg.inv(A)
 
 
-@pytest.mark.parametrize("nu,omega", [(2, 0.7), (1, 0.9)])
-def test_vcycle_closed_form_and_spd(nu, omega, pr2, pr3, pr3h):
-    """(2, 0.7): the configs' smoother; (1, 0.9): the benchmark's."""
+@pytest.mark.parametrize("nu,omega,nu_c", [(2, 0.7, 0), (1, 0.9, 0), (1, 0.9, 3)])
+def test_vcycle_closed_form_and_spd(nu, omega, nu_c, pr2, pr3, pr3h):
+    """(2, 0.7): the configs' smoother; (1, 0.9): one sweep on every level;
+    (1, 0.9) with 3 sweeps on the levels below the finest: the benchmark's."""
     for pr in (pr2, pr3, pr3h):
-        H = mg.hierarchy_of(pr, omega=omega, nu=nu)
+        H = mg.hierarchy_of(pr, omega=omega, nu=nu, nu_coarse=nu_c)
         L = H.A[0].shape[0]
         B = np.column_stack([H.vcycle(e) for e in np.eye(L)])
-        Bd = _vcycle_dense(H, 0)
+        sweeps = [nu] + [nu_c if nu_c > 0 else nu] * (H.nlev - 1)
+        Bd = _vcycle_dense(H, 0, sweeps)
         assert np.abs(B - Bd).max() <= 1e-9 * np.abs(Bd).max()
         assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
         assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0.0

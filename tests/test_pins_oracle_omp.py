@@ -54,6 +54,23 @@ def test_pcg_matches_numpy_oracle(cases, name):
     assert _rel(xc, xo) <= 1e-12
 
 
+def test_coarse_sweeps_match_numpy_oracle(cases):
+    """Three sweeps on the levels below the finest (the benchmark's cycle):
+    the C++ oracle's V-cycle and PCG equal the numpy oracle's."""
+    pr, _, _ = cases["c2n8"]
+    H = mg.hierarchy_of(pr, omega=0.9, nu=1, nu_coarse=3)
+    O = mg_omp.OmpHierarchy(pr, omega=0.9, nu=1, nu_coarse=3)
+    r = np.random.default_rng(7).uniform(-1, 1, H.A[0].shape[0])
+    assert _rel(O.vcycle(r), H.vcycle(r)) <= 1e-12
+    H1 = mg.hierarchy_of(pr, omega=0.9, nu=1)
+    assert _rel(H.vcycle(r), H1.vcycle(r)) > 1e-6          # the count matters
+    b = np.asarray(pr.b).reshape(-1)
+    xo, ho, ito = mg.pcg(H.A[0], b, H.vcycle, rtol=1e-10, maxit=600)
+    xc, hc, itc = O.pcg(b, rtol=1e-10, maxit=600)
+    assert itc == ito and _rel(xc, xo) <= 1e-12
+    O.close()
+
+
 def test_pcg_matches_dense_direct_solve():
     from xdg_inputs.levelset import Quadric
     from xdg_inputs.problems import build
