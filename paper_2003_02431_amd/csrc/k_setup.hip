@@ -67,15 +67,18 @@ __global__ __launch_bounds__(256) void k_extract_list(int n, const int* __restri
     }
 }
 
+// Ac = the leading npc x npc corner of every block (column-major out); the
+// blocks of A are column-major, or row-major (the caller's level-0 values)
+// when row_major is set
 __global__ void k_extract_leading(int64_t nnzb, int npf, int npc, const double* __restrict__ A,
-                                  double* __restrict__ Ac) {
+                                  double* __restrict__ Ac, int row_major) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nc2 = (int64_t)npc * npc;
     if (t >= nnzb * nc2) return;
     const int64_t b = t / nc2;
     const int e = (int)(t - b * nc2);
     const int c = e / npc, r = e - c * npc;
-    Ac[t] = A[b * npf * npf + (int64_t)c * npf + r];
+    Ac[t] = A[b * npf * npf + (row_major ? (int64_t)r * npf + c : (int64_t)c * npf + r)];
 }
 
 // (M R)_k for the blocks k = (i, J) of the aggregation-level product: sum over
@@ -696,8 +699,9 @@ template void launch_gather_blocks<double, double>(hipStream_t, int64_t, int, co
 template void launch_gather_blocks<double, float>(hipStream_t, int64_t, int, const int*,
                                                   const double*, float*);
 void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const double* A,
-                            double* Ac) {
-    k_extract_leading<<<nblk(nnzb * npc * npc, 256), 256, 0, s>>>(nnzb, npf, npc, A, Ac);
+                            double* Ac, bool row_major) {
+    k_extract_leading<<<nblk(nnzb * npc * npc, 256), 256, 0, s>>>(nnzb, npf, npc, A, Ac,
+                                                                   row_major ? 1 : 0);
 }
 void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
                            const int* cfb, const int* crow, const int* ccol, const double* A,

@@ -238,11 +238,11 @@ static int invert_coarsest(xdg_handle* h, Level& lv) {
 
 // the level's derived FP64 copies from its full FP64 blocks: the symmetric
 // level's upper blocks and the leading columns (FP32 ones: convert_level32)
-static void sym_refresh(xdg_handle* h, Level& lv) {
+static void sym_refresh(Level& lv, hipStream_t s) {
     if (lv.sym)
-        launch_gather_blocks<double, double>(h->s, lv.nnzb_u, lv.np * lv.np, lv.ufull, lv.A64,
+        launch_gather_blocks<double, double>(s, lv.nnzb_u, lv.np * lv.np, lv.ufull, lv.A64,
                                              lv.As64);
-    if (lv.AP64) launch_leading_columns<double>(h->s, lv.nnzb, lv.np, lv.npc, lv.A64, lv.AP64);
+    if (lv.AP64) launch_leading_columns<double>(s, lv.nnzb, lv.np, lv.npc, lv.A64, lv.AP64);
 }
 
 // FP32 copies of a level's operator and cell inverses (mixed precision)
@@ -259,18 +259,30 @@ static void convert_level32(Level& lv, hipStream_t s) {
 // Numeric phase of the set-up from level-0 values `raw` (device, row-major
 // blocks): layout change, Galerkin chain, cell-block and coarsest inverses,
 // FP32 copies.  Errors of the inversions are reported through d_err.
+//
+// The coarsest inverse (a chain of small launches) is the critical path, so
+// the handle's stream runs only the Galerkin chain down to it and the
+// inverse; when level 1 is a p-truncation its blocks are the leading corners
+// of the caller's row-major blocks, and the chain starts at once.  The chain's
+// products are latency-bound and slow down several times beside a streaming
+// kernel, so the side stream starts once they are done: it changes level 0's
+// layout (column-major blocks, symmetric upper blocks, leading columns),
+// inverts the cell blocks of every level, forms the M R products and the FP32
+// copies while the coarsest inverse runs.  Both streams are joined before
+// anything reads the result.
 static int numeric_setup(xdg_handle* h, const double* raw) {
-    hipStream_t s = h->s;
+    hipStream_t s = h->s, s2 = h->s2;
     const int nl = (int)h->L.size();
     HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), s));
     Level& L0 = h->L[0];
-    launch_transpose_blocks<double>(s, L0.nnzb, L0.np, raw, L0.A64);
-    sym_refresh(h, L0);
+    const bool from_raw = nl > 1 && L0.t_kind == XDG_T_PTRUNC;
+    if (!from_raw)                           // the chain (or the inverse) reads L0.A64
+        launch_transpose_blocks<double>(s, L0.nnzb, L0.np, raw, L0.A64);
     for (int t = 0; t + 1 < nl; ++t) {
         Level& f = h->L[t];
         Level& c = h->L[t + 1];
         if (f.t_kind == XDG_T_PTRUNC)
-            launch_extract_leading(s, f.nnzb, f.np, c.np, f.A64, c.A64);
+            launch_extract_leading(s, f.nnzb, f.np, c.np, t == 0 ? raw : f.A64, c.A64, t == 0);
         else if (f.g_U)
             launch_galerkin_wide(s, f.n_grp, c.nnzb, f.np, c.np, f.g_gstart, f.g_grow, f.g_cbg,
                                  f.g_fb, f.g_col, f.A64, f.R64, f.g_U, c.A64);
@@ -278,16 +290,15 @@ static int numeric_setup(xdg_handle* h, const double* raw) {
             launch_galerkin_dense(s, c.nnzb, f.np, c.np, f.g_ptr, f.g_fb, f.g_row, f.g_col,
                                   f.A64, f.R64, c.A64, nullptr);
     }
-    // the cell-block inversions and FP32 copies of every level on the side
-    // stream while the coarsest inverse (a chain of small launches) runs on
-    // the handle's stream; joined before anything reads them
     HIPCHK(hipEventRecord(h->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
-    for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l], h->s2));
-    ar_numeric(h, h->s2);
+    HIPCHK(hipStreamWaitEvent(s2, h->ev_fork, 0));
+    if (from_raw) launch_transpose_blocks<double>(s2, L0.nnzb, L0.np, raw, L0.A64);
+    sym_refresh(L0, s2);
+    for (int l = 0; l + 1 < nl; ++l) CHK(invert_cells(h, h->L[l], s2));
+    ar_numeric(h, s2);
     if (h->mixed)
-        for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], h->s2);
-    HIPCHK(hipEventRecord(h->ev_join, h->s2));
+        for (int l = 0; l + 1 < nl; ++l) convert_level32(h->L[l], s2);
+    HIPCHK(hipEventRecord(h->ev_join, s2));
     CHK(invert_coarsest(h, h->L[nl - 1]));
     HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
     if (h->nrhs == kNrhs) CHK(mrhs_numeric(h));
@@ -1466,7 +1477,7 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
         const int* bl = h->d_stage + boff[t];
         if (t == 0) {
             launch_transpose_list(s, (int)bcnt[t], bl, lv.np, val_dev, lv.A64);
-            sym_refresh(h, lv);
+            sym_refresh(lv, s);
         } else {
             Level& f = h->L[t - 1];
             if (f.t_kind == XDG_T_PTRUNC)

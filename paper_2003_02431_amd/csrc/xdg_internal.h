@@ -127,7 +127,7 @@ void launch_gather_blocks(hipStream_t s, int64_t n, int bs, const int* idx, cons
 template <typename T>
 void launch_transpose_blocks(hipStream_t s, int64_t nnzb, int np, const double* in, T* out);
 void launch_extract_leading(hipStream_t s, int64_t nnzb, int npf, int npc, const double* A,
-                            double* Ac);
+                            double* Ac, bool row_major = false);
 // list == nullptr: every coarse block / cell 0..n-1; else the n listed ones
 void launch_galerkin_dense(hipStream_t s, int n_cblk, int npf, int npc, const int* cptr,
                            const int* cfb, const int* ci_row, const int* ci_col,
