@@ -771,32 +771,70 @@ struct GrpCfg {
     static constexpr int CH = C * NP;
 };
 
-template <typename T, int NP>
-__device__ __forceinline__ void row_stream_g(int b0, int nb, const int* __restrict__ ci,
-                                             const T* __restrict__ A, const T* __restrict__ x,
-                                             int lane, T (&acc)[GrpCfg<T, NP>::VEC]) {
+// Load steps per pass of grp_stream: two (fewer than 16 blocks' worth).  The
+// level-1 grid of the 32^3 workload (~2,000 workgroups) is resident at once
+// only at 8 waves per SIMD, i.e. at most 64 VGPRs; four or eight steps per
+// pass cost that occupancy and were slower.
+template <typename T, int NP, int NCOL>
+struct GrpPass {
+    static constexpr int CH = GrpCfg<T, NP>::CH;
+    static constexpr int U0 = (16 * NP * NCOL + CH - 1) / CH;
+    static constexpr int U = U0 < 1 ? 1 : (U0 > 2 ? 2 : U0);
+};
+
+// acc += (sum over the nb blocks at b0 of A_b x_col(b)) for one lane group;
+// blocks are NP x NCOL, column-major.  The blocks are streamed U load steps
+// at a time and every load of a pass is issued before its products, so a
+// group waits for one memory round trip per pass, not one per load step (the
+// small levels are latency-bound).
+// With TWO the list holds the blocks of two consecutive block rows (the two
+// species of a cell, adjacent in the row storage); blocks at positions >= nb0
+// belong to the second row and go to acc1.  Lanes past the end of the list
+// load entry 0 and add nothing.  Each lane adds its entries in list order, so
+// a one-row list sums exactly as one row at a time.
+template <typename T, int NP, int NCOL, bool TWO>
+__device__ __forceinline__ void grp_stream(int b0, int nb, int nb0, const int* __restrict__ ci,
+                                           const T* __restrict__ A, const T* __restrict__ x,
+                                           int lane, T (&acc0)[GrpCfg<T, NP>::VEC],
+                                           T (&acc1)[GrpCfg<T, NP>::VEC]) {
     using R = GrpCfg<T, NP>;
-    constexpr int V = R::VEC;
+    constexpr int V = R::VEC, U = GrpPass<T, NP, NCOL>::U;
     const int gl = lane & (kGS - 1), gb = lane - gl;
     const int q = gl % R::L, cl = gl / R::L;
     const bool act = cl < R::C;
-    const int colreg = gl < nb ? ci[b0 + gl] : 0;
-    const T* Ar = A + (int64_t)b0 * (NP * NP);
-    const int E = nb * (NP * NP);
+    const int cr0 = gl < nb ? ci[b0 + gl] : 0;
+    const int cr1 = gl + kGS < nb ? ci[b0 + kGS + gl] : 0;
+    const T* Ar = A + (int64_t)b0 * (NP * NCOL);
+    const int E = nb * (NP * NCOL);
     const int off = cl * NP + q * V;
-    for (int base = 0; base < E; base += R::CH) {
-        const int e = base + off;
-        const bool ok = act && e < E;
-        const int xi = e / NP;
-        const int bb = xi / NP;
-        int col = __shfl(colreg, gb + (bb & (kGS - 1)), 64);
-        if (ok) {
-            if (bb >= kGS) col = ci[b0 + bb];
-            const T xv = x[(int64_t)col * NP + (xi - bb * NP)];
-            T a[V];
-            load_vec<T, V>(Ar + e, a);
+    for (int base = 0; base < E; base += U * R::CH) {
+        T a[U][V], xv[U];
+        int bu[U];
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] += a[v] * xv;
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * R::CH + off;
+            const bool ok = act && e < E;
+            const int ec = ok ? e : 0;
+            const int xi = ec / NP;                // (block, column) index
+            const int bb = xi / NCOL;
+            const int s0 = __shfl(cr0, gb + (bb & (kGS - 1)), 64);
+            const int s1 = __shfl(cr1, gb + (bb & (kGS - 1)), 64);
+            int col = bb < kGS ? s0 : s1;
+            if (bb >= 2 * kGS) col = ci[b0 + bb];
+            xv[u] = x[(int64_t)col * NCOL + (xi - bb * NCOL)];
+            load_vec<T, V>(Ar + ec, a[u]);
+            bu[u] = ok ? bb : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = bu[u] >= 0;
+            const bool second = TWO && bu[u] >= nb0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const T p = a[u][v] * xv[u];
+                if (ok && !second) acc0[v] += p;
+                if (TWO && ok && second) acc1[v] += p;
+            }
         }
     }
 }
@@ -836,7 +874,7 @@ __global__ __launch_bounds__(256) void k_bsr_spmv_g(int n_rows, const int* __res
     T acc[R::VEC];
 #pragma unroll
     for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
-    row_stream_g<T, NP>(beg, nb, ci, A, x, lane, acc);
+    grp_stream<T, NP, NP, false>(beg, nb, nb, ci, A, x, lane, acc, acc);
     reduce_groups_g<T, R::VEC>(acc, R::L, R::C, lane);
     const int gl = lane & (kGS - 1);
     if (valid && gl < R::L) {
@@ -851,6 +889,38 @@ __global__ __launch_bounds__(256) void k_bsr_spmv_g(int n_rows, const int* __res
     }
 }
 
+// Right-hand side of a cell of at most two block rows in the reduction's
+// layout (lanes 0..L-1), loaded before the streams (it needs only the cell's
+// first row); the cell's inverse is applied after the residual is in LDS,
+// every column's load issued at once (lane o < nc owns unknown o).
+template <typename T, int NP>
+struct CellPre {
+    static constexpr int CM = 2 * NP;
+    T b0[GrpCfg<T, NP>::VEC], b1[GrpCfg<T, NP>::VEC];
+    __device__ __forceinline__ void load(const T* __restrict__ b, int64_t base, int nr, int gl) {
+        constexpr int V = GrpCfg<T, NP>::VEC;
+        const int r = min(gl, GrpCfg<T, NP>::L - 1) * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            b0[v] = nr > 0 ? b[base + r + v] : T(0);
+            b1[v] = nr > 1 ? b[base + NP + r + v] : T(0);
+        }
+    }
+    // (D_c res)_o for lane o = gl < nc of the column-major nc x nc inverse Dc
+    __device__ __forceinline__ static T apply(const T* __restrict__ Dc, const T* res, int nc,
+                                              int gl) {
+        const int o = min(gl, max(nc - 1, 0));
+        T d[CM];
+#pragma unroll
+        for (int c = 0; c < CM; ++c) d[c] = Dc[(int64_t)min(c, max(nc - 1, 0)) * nc + o];
+        T a = 0;
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+            if (c < nc) a += d[c] * res[c];
+        return a;
+    }
+};
+
 template <typename T, int NP, bool FIRST>
 __global__ __launch_bounds__(256) void k_jacobi_g(int n_cells, const int* __restrict__ cell_ptr,
                                                   const int* __restrict__ rp,
@@ -862,7 +932,9 @@ __global__ __launch_bounds__(256) void k_jacobi_g(int n_cells, const int* __rest
                                                   const T* __restrict__ xin,
                                                   T* __restrict__ xout, T omega) {
     using R = GrpCfg<T, NP>;
+    constexpr int V = R::VEC;
     constexpr int G = 256 / kGS;
+    static_assert(2 * NP <= kGS, "a two-row cell must fit one lane group");
     __shared__ T res[G][kMaxCell];
     const int lane = threadIdx.x & 63;
     const int grp = threadIdx.x / kGS, gl = lane & (kGS - 1);
@@ -873,20 +945,49 @@ __global__ __launch_bounds__(256) void k_jacobi_g(int n_cells, const int* __rest
         r0 = cell_ptr[cell];
         r1 = cell_ptr[cell + 1];
     }
-    const int nc = (r1 - r0) * NP;                 // <= kMaxCell (checked on the host)
-    for (int row = r0; row < r1; ++row) {
-        T acc[R::VEC];
+    const int nr = r1 - r0;
+    const int nc = nr * NP;                        // <= kMaxCell (checked on the host)
+    const int64_t base = (int64_t)r0 * NP;
+    if (nr <= 2) {
+        CellPre<T, NP> pre;
+        pre.load(b, base, nr, gl);
+        const T* Dc = D + (valid ? doff[cell] : 0);
+        const T xo = !FIRST && gl < nc ? xin[base + gl] : T(0);
+        T acc0[V], acc1[V];
 #pragma unroll
-        for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
-        if (!FIRST) {
-            const int beg = rp[row], nb = rp[row + 1] - beg;
-            row_stream_g<T, NP>(beg, nb, ci, A, xin, lane, acc);
-            reduce_groups_g<T, R::VEC>(acc, R::L, R::C, lane);
+        for (int v = 0; v < V; ++v) acc0[v] = acc1[v] = 0;
+        if (!FIRST && nr > 0) {
+            const int beg = rp[r0], mid = rp[r0 + 1], end = rp[r1];
+            grp_stream<T, NP, NP, true>(beg, end - beg, mid - beg, ci, A, xin, lane, acc0, acc1);
+            reduce_groups_g<T, V>(acc0, R::L, R::C, lane);
+            reduce_groups_g<T, V>(acc1, R::L, R::C, lane);
         }
         if (gl < R::L) {
 #pragma unroll
-            for (int v = 0; v < R::VEC; ++v) {
-                const int r = gl * R::VEC + v;
+            for (int v = 0; v < V; ++v) {
+                res[grp][gl * V + v] = pre.b0[v] - acc0[v];
+                res[grp][NP + gl * V + v] = pre.b1[v] - acc1[v];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (gl < nc) xout[base + gl] = xo + omega * CellPre<T, NP>::apply(Dc, res[grp], nc, gl);
+        return;
+    }
+    for (int row = r0; row < r1; ++row) {
+        T acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0;
+        if (!FIRST) {
+            const int beg = rp[row], nb = rp[row + 1] - beg;
+            grp_stream<T, NP, NP, false>(beg, nb, nb, ci, A, xin, lane, acc, acc);
+            reduce_groups_g<T, V>(acc, R::L, R::C, lane);
+        }
+        if (gl < R::L) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int r = gl * V + v;
                 res[grp][(row - r0) * NP + r] = b[(int64_t)row * NP + r] - acc[v];
             }
         }
@@ -894,14 +995,11 @@ __global__ __launch_bounds__(256) void k_jacobi_g(int n_cells, const int* __rest
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (valid) {
-        const T* Dc = D + doff[cell];
-        const int64_t base = (int64_t)r0 * NP;
-        for (int o = gl; o < nc; o += kGS) {
-            T a = 0;
-            for (int c = 0; c < nc; ++c) a += Dc[(int64_t)c * nc + o] * res[grp][c];
-            xout[base + o] = (FIRST ? T(0) : xin[base + o]) + omega * a;
-        }
+    const T* Dc = D + doff[cell];
+    for (int o = gl; o < nc; o += kGS) {
+        T a = 0;
+        for (int c = 0; c < nc; ++c) a += Dc[(int64_t)c * nc + o] * res[grp][c];
+        xout[base + o] = (FIRST ? T(0) : xin[base + o]) + omega * a;
     }
 }
 
@@ -913,37 +1011,6 @@ __global__ __launch_bounds__(256) void k_jacobi_g(int n_cells, const int* __rest
 // M_ij R_j (np x npc, column-major, formed at set-up; the distinct coarse
 // neighbours of a row are fewer than its fine ones).  One 16-lane group per
 // cell, as k_jacobi_g; the prolongation is fused.
-template <typename T, int NP, int NC>
-__device__ __forceinline__ void row_stream_nc_g(int b0, int nb, const int* __restrict__ ci,
-                                                const T* __restrict__ AR,
-                                                const T* __restrict__ e, int lane,
-                                                T (&acc)[GrpCfg<T, NP>::VEC]) {
-    using R = GrpCfg<T, NP>;
-    constexpr int V = R::VEC;
-    const int gl = lane & (kGS - 1), gb = lane - gl;
-    const int q = gl % R::L, cl = gl / R::L;
-    const bool act = cl < R::C;
-    const int colreg = gl < nb ? ci[b0 + gl] : 0;
-    const T* Ar = AR + (int64_t)b0 * (NP * NC);
-    const int E = nb * (NP * NC);
-    const int off = cl * NP + q * V;
-    for (int base = 0; base < E; base += R::CH) {
-        const int ee = base + off;
-        const bool ok = act && ee < E;
-        const int xi = ee / NP;
-        const int bb = xi / NC;
-        int col = __shfl(colreg, gb + (bb & (kGS - 1)), 64);
-        if (ok) {
-            if (bb >= kGS) col = ci[b0 + bb];
-            const T ev = e[(int64_t)col * NC + (xi - bb * NC)];
-            T a[V];
-            load_vec<T, V>(Ar + ee, a);
-#pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] += a[v] * ev;
-        }
-    }
-}
-
 template <typename T, int NP, int NC>
 __global__ __launch_bounds__(256) void k_jacobi_cc_g(int n_cells, const int* __restrict__ cell_ptr,
                                                      const int* __restrict__ arp,
@@ -959,7 +1026,9 @@ __global__ __launch_bounds__(256) void k_jacobi_cc_g(int n_cells, const int* __r
                                                      const T* __restrict__ Rt,
                                                      T* __restrict__ xout, T omega) {
     using R = GrpCfg<T, NP>;
+    constexpr int V = R::VEC;
     constexpr int G = 256 / kGS;
+    static_assert(2 * NP <= kGS, "a two-row cell must fit one lane group");
     __shared__ T res[G][kMaxCell];
     const int lane = threadIdx.x & 63;
     const int grp = threadIdx.x / kGS, gl = lane & (kGS - 1);
@@ -970,18 +1039,58 @@ __global__ __launch_bounds__(256) void k_jacobi_cc_g(int n_cells, const int* __r
         r0 = cell_ptr[cell];
         r1c = cell_ptr[cell + 1];
     }
-    const int nc = (r1c - r0) * NP;                // <= kMaxCell (checked on the host)
-    for (int row = r0; row < r1c; ++row) {
-        T acc[R::VEC];
+    const int nr = r1c - r0;
+    const int nc = nr * NP;                        // <= kMaxCell (checked on the host)
+    const int64_t base = (int64_t)r0 * NP;
+    if (nr <= 2) {
+        CellPre<T, NP> pre;
+        pre.load(r1, base, nr, gl);
+        const T* Dc = D + (valid ? doff[cell] : 0);
+        // x1 and the prolongation R_i e_parent(i) of unknown gl
+        const int og = min(gl, max(nc - 1, 0));
+        const int row = r0 + og / NP, a = og % NP;
+        T xo = 0;
+        if (gl < nc) {
+            const T* Ri = Rt + (int64_t)ridx[row] * NP * NC + a * NC;
+            const T* ep = e + (int64_t)parent[row] * NC;
+            T pe = 0;
 #pragma unroll
-        for (int v = 0; v < R::VEC; ++v) acc[v] = 0;
-        const int beg = arp[row], nb = arp[row + 1] - beg;
-        row_stream_nc_g<T, NP, NC>(beg, nb, arc, AR, e, lane, acc);
-        reduce_groups_g<T, R::VEC>(acc, R::L, R::C, lane);
+            for (int m = 0; m < NC; ++m) pe += Ri[m] * ep[m];
+            xo = x1[base + gl] + pe;
+        }
+        T acc0[V], acc1[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc0[v] = acc1[v] = 0;
+        if (nr > 0) {
+            const int beg = arp[r0], mid = arp[r0 + 1], end = arp[r1c];
+            grp_stream<T, NP, NC, true>(beg, end - beg, mid - beg, arc, AR, e, lane, acc0, acc1);
+            reduce_groups_g<T, V>(acc0, R::L, R::C, lane);
+            reduce_groups_g<T, V>(acc1, R::L, R::C, lane);
+        }
         if (gl < R::L) {
 #pragma unroll
-            for (int v = 0; v < R::VEC; ++v) {
-                const int r = gl * R::VEC + v;
+            for (int v = 0; v < V; ++v) {
+                res[grp][gl * V + v] = pre.b0[v] - acc0[v];
+                res[grp][NP + gl * V + v] = pre.b1[v] - acc1[v];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (gl < nc) xout[base + gl] = xo + omega * CellPre<T, NP>::apply(Dc, res[grp], nc, gl);
+        return;
+    }
+    for (int row = r0; row < r1c; ++row) {
+        T acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0;
+        const int beg = arp[row], nb = arp[row + 1] - beg;
+        grp_stream<T, NP, NC, false>(beg, nb, nb, arc, AR, e, lane, acc, acc);
+        reduce_groups_g<T, V>(acc, R::L, R::C, lane);
+        if (gl < R::L) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int r = gl * V + v;
                 res[grp][(row - r0) * NP + r] = r1[(int64_t)row * NP + r] - acc[v];
             }
         }
@@ -989,19 +1098,16 @@ __global__ __launch_bounds__(256) void k_jacobi_cc_g(int n_cells, const int* __r
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (valid) {
-        const T* Dc = D + doff[cell];
-        const int64_t base = (int64_t)r0 * NP;
-        for (int o = gl; o < nc; o += kGS) {
-            const int row = r0 + o / NP, a = o % NP;
-            const T* Ri = Rt + (int64_t)ridx[row] * NP * NC + a * NC;
-            const T* ep = e + (int64_t)parent[row] * NC;
-            T pe = 0;
-            for (int m = 0; m < NC; ++m) pe += Ri[m] * ep[m];
-            T acc = 0;
-            for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * res[grp][c];
-            xout[base + o] = (x1[base + o] + pe) + omega * acc;
-        }
+    const T* Dc = D + doff[cell];
+    for (int o = gl; o < nc; o += kGS) {
+        const int row = r0 + o / NP, a = o % NP;
+        const T* Ri = Rt + (int64_t)ridx[row] * NP * NC + a * NC;
+        const T* ep = e + (int64_t)parent[row] * NC;
+        T pe = 0;
+        for (int m = 0; m < NC; ++m) pe += Ri[m] * ep[m];
+        T acc = 0;
+        for (int c = 0; c < nc; ++c) acc += Dc[(int64_t)c * nc + o] * res[grp][c];
+        xout[base + o] = (x1[base + o] + pe) + omega * acc;
     }
 }
 
