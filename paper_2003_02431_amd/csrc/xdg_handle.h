@@ -152,6 +152,7 @@ struct xdg_handle {
     hipStream_t s = nullptr;
     hipStream_t s2 = nullptr;       // side stream of the numeric set-up
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_scal = nullptr;              // CG scalars copied to the host
     int dev = 0;                    // device current at xdg_create
     xdg_options opt{};
     std::vector<Level> L;
