@@ -1498,7 +1498,6 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
         const int* bl = h->d_stage + boff[t];
         if (t == 0) {
             launch_transpose_list(s, (int)bcnt[t], bl, lv.np, val_dev, lv.A64);
-            sym_refresh(lv, s);
         } else {
             Level& f = h->L[t - 1];
             if (f.t_kind == XDG_T_PTRUNC)
@@ -1511,10 +1510,12 @@ extern "C" int xdg_update_cells(xdg_handle* h, const double* val_dev, int32_t n,
                                       f.g_col, f.A64, f.R64, lv.A64, bl);
         }
     }
-    // the listed cells' inversions and the FP32 copies on the side stream while
-    // the coarsest inverse is rebuilt, as in the full set-up
+    // level 0's symmetric copies, the listed cells' inversions and the FP32
+    // copies on the side stream while the coarsest inverse is rebuilt, as in
+    // the full set-up
     HIPCHK(hipEventRecord(h->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
+    sym_refresh(h->L[0], h->s2);
     for (int t = 0; t + 1 < nl; ++t) {
         if (ccnt[t] == 0) continue;
         Level& lv = h->L[t];
