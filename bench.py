@@ -11,8 +11,10 @@ measured setting; 2 / 2 everywhere at omega 0.7 is --nu 2 --omega 0.7
 One step = the whole hot path on device-resident input: numeric hierarchy
 set-up from the level-0 values (Galerkin products, cell-block and coarsest
 inversions; xdg_update_matrix) followed by the PCG solve to rel.res 1e-8
-(xdg_solve).  `value` is the time of one step in seconds (lower is better).
-The JSON line also carries the level-0 block-SpMV roofline (HIP events around
+(xdg_solve).  `value` is the time of one step in seconds (lower is better);
+`setup_ms` is the step's own set-up (median of five warm xdg_update_matrix
+calls), `setup_first_ms` the one at handle creation, which also pays every
+kernel's first launch.  The JSON line also carries the level-0 block-SpMV roofline (HIP events around
 back-to-back launches on the solver's stream), the time to 1e-10, the
 mixed-precision forms, the orthonormalisation multigrid, and the plain-loop
 C++ oracle's own set-up and solve of the same problem on every host core;
