@@ -1278,7 +1278,11 @@ extern "C" int xdg_solve(xdg_handle* h, const double* b, double* x, double* hist
              : h->opt.krylov == XDG_FGMRES ? solve_fgmres(h, b, x, hist, hist_cap, &it)
                                            : xdg::solve_orthomg(h, b, x, hist, hist_cap, &it);
     *iters = it;
-    if (rc < 0) return rc;
+    if (rc < 0) {
+        // work the solver enqueued ahead of its last test may still be running
+        (void)hipStreamSynchronize(h->s);
+        return rc;
+    }
     CHK(true_relres(h, b, x, final_relres));
     if (rc == XDG_ENOCONV) fail(0, "xdg_solve: iteration limit reached");
     return rc;
