@@ -19,7 +19,9 @@
  *   - *_dev pointers are caller-owned device buffers on the handle's device;
  *     outputs must not alias inputs.
  *   - every call is enqueued on the handle's HIP stream; only xdg_create,
- *     xdg_solve and the xdg_get_* copies synchronise it.
+ *     the set-up calls xdg_update_matrix / xdg_update_cells (they report
+ *     non-positive pivots), xdg_solve and the xdg_get_* copies synchronise
+ *     it, and those return with the stream idle.
  *   - vectors are FP64, laid out [block row][mode] (row-major), length
  *     n_rows * np of the level they live on; a handle created with
  *     nrhs = 16 takes 16 columns per vector, laid out [block row][mode][16].
